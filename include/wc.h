@@ -1,0 +1,175 @@
+/*
+ * wc.h - C interface of libwc, the MI355X (gfx950) Wilson-clover SAP-FGCR library.
+ *
+ * The method is the mixed-precision Schwarz-preconditioned flexible GCR solver for the
+ * Wilson-Dirac operator with clover term of A. Nobile, "Solving the Dirac equation on
+ * QPACE" (arXiv:1109.4279): abstract and Sec. 4 (operator, SAP, MR block solver, FGCR,
+ * mixed precision by iterative refinement), Sec. 5 (block-contiguous field layout),
+ * Sec. 1 (the solves feed the HMC fermion force).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice      dims[4] = (L0, L1, L2, L3), axis 0 = time.  Sites are lexicographic with
+ *              x3 fastest.  Every L_mu must be a multiple of the Schwarz block extent b_mu
+ *              and L_mu / b_mu must be even (chessboard colouring of the blocks, Sec. 4);
+ *              blocks hold at most 256 sites.
+ * Operator     D psi(x) = A(x) psi(x) - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *                                               + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu)],
+ *              A = (4 + m0) + c_sw (i/4) sigma_{mu nu} F_{mu nu}, F the clover-leaf field
+ *              strength (Q - Q^dag)/8; chiral gamma basis g0 = [[0,-1],[-1,0]],
+ *              gk = [[0,-i s_k],[i s_k,0]], g5 = diag(1,1,-1,-1).
+ * Gauge field  complex128 (interleaved re, im) U[4][L0][L1][L2][L3][3][3], row-major 3x3;
+ *              U[mu] at x is the link x -> x + mu.
+ * Spinors      complex128 psi[nrhs][L0][L1][L2][L3][4][3] (spin, then colour).
+ * Pointers     every array argument is a DEVICE pointer on the current HIP device,
+ *              owned by the caller, contiguous, at least 16-byte aligned.  The library
+ *              copies what it keeps (the links) and never frees caller memory.
+ * Streams      `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *              it; only the solver entry points synchronise (once per FGCR restart, to
+ *              read the residual norms) and say so.
+ * Errors       every int-returning function returns WC_OK (0) or a negative wc_status;
+ *              wc_last_error() gives a message for the calling thread.  Nothing throws
+ *              across this interface.  On an error no output has been written unless
+ *              the entry point says otherwise.
+ */
+#ifndef WC_H
+#define WC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wc_ctx wc_ctx;
+
+typedef enum {
+  WC_OK = 0,
+  WC_ERR_ARG = -1,           /* null pointer, nrhs < 1, bad enum or parameter */
+  WC_ERR_GEOMETRY = -2,      /* lattice / block shape not allowed (see above) */
+  WC_ERR_HIP = -3,           /* HIP runtime error; message kept */
+  WC_ERR_OOM = -4,           /* device allocation failed */
+  WC_ERR_NOT_CONVERGED = -5, /* solve stopped at maxit; x and stats are written */
+  WC_ERR_BREAKDOWN = -6,     /* NaN/Inf or a vanishing Krylov direction; x and stats written */
+  WC_ERR_STATE = -7          /* clover term not created yet */
+} wc_status;
+
+/* Storage / arithmetic precision of a kernel.  WC_F16S and WC_BF16S store spinors,
+ * links and clover blocks in 16 bits with an FP32 scale per site (per chirality block for
+ * the clover) and compute in FP32. */
+typedef enum { WC_F64 = 0, WC_F32 = 1, WC_F16S = 2, WC_BF16S = 3 } wc_prec;
+
+typedef enum { WC_FULL = 0, WC_BLOCKS = 1 } wc_region;
+
+typedef struct {
+  int nkv;       /* FGCR restart length, 1..32 (Sec. 4: two vectors stored per iteration) */
+  int ncy;       /* SAP cycles per preconditioner application, >= 1 */
+  int nmr;       /* MR steps per block, >= 1 (Sec. 4: fixed iteration count) */
+  int sap_prec;  /* wc_prec of the preconditioner: WC_F64 = plain method, else mixed */
+  double tol;    /* stop when ||b - D x|| / ||b|| <= tol, recomputed in FP64 */
+  int maxit;     /* cap on FGCR iterations per right-hand side */
+  int x0_given;  /* 1: x holds the initial guess (restart point), 0: start from x = 0 */
+  int use_graph; /* 1: replay each restart cycle as one captured hipGraph */
+  int nr_dirac;  /* right-hand sides per lane in D (0: library / autotuned choice) */
+  int nr_sap;    /* right-hand sides per work-group in the block solver (0: library choice) */
+} wc_solver_params;
+
+typedef struct {
+  int status;          /* wc_status of this right-hand side */
+  int iters;           /* FGCR iterations */
+  int restarts;        /* restart cycles, each ending in an FP64 true residual */
+  int breakdown;       /* 1 if the recursion broke down (NaN/Inf or zero direction) */
+  double rel_true_res; /* last FP64 ||b - D x|| / ||b|| */
+  double time_ms;      /* solve time of the whole call (same for every rhs of a call) */
+} wc_solver_stats;
+
+/* Fill p with the library defaults: nkv 16, ncy 5, nmr 4, sap_prec WC_F32, tol 1e-10,
+ * maxit 10000, no initial guess, graphs on, automatic RHS tiles. */
+void wc_default_params(wc_solver_params* p);
+
+/* Create a context for one lattice: copies the gauge field U (device, complex128, see
+ * above) and lays it out block-major with Schwarz blocks block[4] (Sec. 5: points of one
+ * block are contiguous).  bc_t = +1 periodic, -1 antiperiodic fermions in time.
+ * Errors: WC_ERR_ARG (null), WC_ERR_GEOMETRY (dims/block), WC_ERR_OOM, WC_ERR_HIP. */
+int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const void* U, int bc_t, void* stream);
+
+/* Build the clover blocks A_+-(x) from the links: (4 + m0) + c_sw (i/4) sigma F (abstract,
+ * Sec. 4; two 6x6 Hermitian chiral blocks per site).  Replaces any previous clover. */
+int wc_create_clover(wc_ctx* ctx, double m0, double csw, void* stream);
+
+/* Re-lay the context out for another Schwarz block shape (used by the autotuner). */
+int wc_set_block(wc_ctx* ctx, const int block[4], void* stream);
+
+/* Copy the clover blocks out: A[V][2][6][6] complex128 (lexicographic sites; block 0 acts
+ * on spins 0,1, block 1 on spins 2,3; row index 3*spin + colour), Hermitian-completed. */
+int wc_clover_export(wc_ctx* ctx, void* A, void* stream);
+
+/* out = D in (region WC_FULL) or the block-diagonal sum of the Dirichlet block operators
+ * D_Lambda in (WC_BLOCKS: hops between different blocks dropped, Sec. 4).  dagger = 1
+ * applies D^dag = g5 D g5.  prec selects storage/arithmetic; inputs and outputs are
+ * complex128 in any case (converted on the device).  in and out must not overlap. */
+int wc_apply_D(wc_ctx* ctx, void* out, const void* in, int nrhs, int prec, int region, int dagger, void* stream);
+
+/* One Schwarz half-sweep (Sec. 4): nmr MR steps from a zero start on every block of the
+ * given colour, source rho.  On return z holds the block solutions on that colour and 0
+ * elsewhere; rho holds the MR residual on that colour and 0 elsewhere. */
+int wc_sap_block_mr(wc_ctx* ctx, void* z, void* rho, int nrhs, int colour, int nmr, int prec, void* stream);
+
+/* psi = M_SAP eta: ncy cycles of the Schwarz alternating procedure from psi = 0 (Sec. 4):
+ * white blocks, residual update on their neighbours' borders, black blocks, update. */
+int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, void* stream);
+
+/* Solve D x = b for nrhs right-hand sides with SAP-preconditioned restarted FGCR (Sec. 4).
+ * The preconditioner runs in p->sap_prec; chi = D phi, Gram-Schmidt, the residual update,
+ * the solution update and the true residual stay in FP64.  st (may be NULL) receives nrhs
+ * entries.  Synchronises `stream` once per restart.  Returns WC_OK when every rhs
+ * converged, else the first failing status (x is written regardless). */
+int wc_fgcr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_solver_params* p, wc_solver_stats* st,
+                  void* stream);
+
+/* The same for nlat lattices of different sizes solved together: every kernel of the
+ * solve is one launch over all lattices and right-hand sides.  x[i], b[i] are the
+ * lattice-i arrays with nrhs[i] right-hand sides; st receives sum(nrhs) entries. */
+int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
+                        const wc_solver_params* p, wc_solver_stats* st, void* stream);
+
+/* G = coef * dL/dU for L = sum_r Re <Y_r, D X_r> in torch's complex-gradient convention
+ * (dL = Re sum tr(G^dag dU)), complex128 [4][L0..L3][3][3].  Hopping and clover terms
+ * (product rule over the plaquette leaves).  Used for the backward of D and of D^-1. */
+int wc_link_grad(wc_ctx* ctx, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream);
+
+/* Pseudofermion force of S = phi^dag (D^dag D)^-1 phi (Sec. 1: the HMC force from the
+ * fermion determinant): Y = D^-dag phi and X = D^-1 Y by two solves with p, then
+ * F_mu(x) = sum_a (dS/d eps_a) T^a for U_mu(x) -> exp(eps_a T^a) U_mu(x), T^a = i lambda_a / 2,
+ * a traceless anti-Hermitian complex128 [4][L0..L3][3][3].  Y, X may be NULL or receive
+ * the two solutions (complex128 spinors).  st (may be NULL) gets 2 entries. */
+int wc_force(wc_ctx* ctx, void* F, const void* phi, const wc_solver_params* p, wc_solver_stats* st, void* Y,
+             void* X, void* stream);
+
+/* Autotune: time the RHS tile of D and of the block solver for (nrhs, prec) and keep the
+ * fastest in the context; nr_out[0..1] receive the chosen (D, SAP) tiles. */
+int wc_autotune(wc_ctx* ctx, int nrhs, int prec, int nr_out[2], void* stream);
+
+/* Choose the Schwarz block shape of the context among the valid shapes with at most 256
+ * sites by timing a short solve (tolerance p->tol) of one Gaussian source for each;
+ * re-lays the context out for the fastest.  block_out receives it. */
+int wc_autotune_block(wc_ctx* ctx, const wc_solver_params* p, int block_out[4], void* stream);
+
+/* Timing helpers for the benchmark: run the D kernel (or one Schwarz half-sweep) iters
+ * times back to back on internal fields between two HIP events on `stream`; *ms gets the
+ * mean time per launch.  Synchronises `stream`. */
+int wc_bench_dirac(wc_ctx* ctx, int prec, int nrhs, int region, int iters, double* ms, void* stream);
+int wc_bench_sap(wc_ctx* ctx, int prec, int nrhs, int nmr, int iters, double* ms, void* stream);
+
+/* Release everything the context owns. */
+void wc_destroy(wc_ctx* ctx);
+
+/* Message of the last error on this thread (static storage, valid until the next call). */
+const char* wc_last_error(void);
+
+/* Interface version: 100 * major + minor. */
+int wc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WC_H */

@@ -1,0 +1,221 @@
+"""MI355X-native Wilson-clover SAP-FGCR hot path (arXiv:1109.4279) behind a C interface.
+
+Python holds device memory (torch tensors) and marshals arguments; every step of the
+operator, the Schwarz preconditioner, the Krylov solver and the force runs in the HIP
+library ``libwc.so`` (see ``include/wc.h``).  Importing this package does not load the
+library; the first call does, and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import PREC, REGION, SolverParams, SolverStats, WCError  # noqa: F401
+
+__all__ = ["Lattice", "SolverParams", "SolverStats", "WCError", "default_params", "solve_batch", "PREC"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, shape_tail=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise WCError(-1, f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.complex128:
+        raise WCError(-1, f"{name} must be complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise WCError(-1, f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise WCError(-1, f"{name} has shape {tuple(t.shape)}, expected (..., {shape_tail})")
+    return t
+
+
+def default_params(**kw) -> SolverParams:
+    p = SolverParams()
+    _lib.load().wc_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "sap_prec" and isinstance(v, str):
+            v = PREC[v]
+        setattr(p, k, v)
+    return p
+
+
+class Lattice:
+    """One lattice: gauge field, clover term and the library context that owns their copies.
+
+    U: complex128 CUDA tensor [4][L0][L1][L2][L3][3][3]; block: Schwarz block shape."""
+
+    def __init__(self, U, block=(4, 4, 4, 4), m0: float = 0.0, csw: float = 1.0, bc_t: int = 1, stream=None):
+        lib = _lib.load()
+        _need(U, "U", (3, 3))
+        self.dims = tuple(int(d) for d in U.shape[1:5])
+        self.block = tuple(int(b) for b in block)
+        self.m0, self.csw, self.bc_t = float(m0), float(csw), int(bc_t)
+        self._U = U
+        self._ctx = ctypes.c_void_p()
+        dims = (ctypes.c_int * 4)(*self.dims)
+        blk = (ctypes.c_int * 4)(*self.block)
+        _lib.check(lib.wc_create_gauge(ctypes.byref(self._ctx), dims, blk, _ptr(U), self.bc_t, _stream(stream)))
+        _lib.check(lib.wc_create_clover(self._ctx, self.m0, self.csw, _stream(stream)))
+
+    @property
+    def volume(self) -> int:
+        v = 1
+        for d in self.dims:
+            v *= d
+        return v
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            try:
+                _lib.load().wc_destroy(ctx)
+            except Exception:
+                pass
+            self._ctx = None
+
+    # ------------------------------------------------------------------ helpers
+    def _spinor(self, t, name):
+        _need(t, name, self.dims + (4, 3))
+        nrhs = 1 if t.dim() == 6 else int(t.numel() // (self.volume * 12))
+        return nrhs
+
+    def new_spinor(self, nrhs=None):
+        torch = _torch()
+        shape = self.dims + (4, 3) if nrhs is None else (nrhs,) + self.dims + (4, 3)
+        return torch.empty(shape, dtype=torch.complex128, device=self._U.device)
+
+    # ------------------------------------------------------------------ operator
+    def apply_D(self, x, prec="f64", region="full", dagger=False, out=None, stream=None):
+        nrhs = self._spinor(x, "x")
+        out = self.new_spinor(None if x.dim() == 6 else nrhs) if out is None else out
+        _lib.check(_lib.load().wc_apply_D(self._ctx, _ptr(out), _ptr(x), nrhs, PREC[prec], REGION[region],
+                                          int(bool(dagger)), _stream(stream)))
+        return out
+
+    def clover(self, stream=None):
+        torch = _torch()
+        A = torch.empty(self.dims + (2, 6, 6), dtype=torch.complex128, device=self._U.device)
+        _lib.check(_lib.load().wc_clover_export(self._ctx, _ptr(A), _stream(stream)))
+        return A
+
+    def sap_block_mr(self, rho, colour, nmr, prec="f64", stream=None):
+        """One half-sweep: returns (z, rho_new) as the library computes them (rho is not modified)."""
+        nrhs = self._spinor(rho, "rho")
+        r = rho.clone()
+        z = self.new_spinor(None if rho.dim() == 6 else nrhs)
+        _lib.check(_lib.load().wc_sap_block_mr(self._ctx, _ptr(z), _ptr(r), nrhs, int(colour), int(nmr), PREC[prec],
+                                               _stream(stream)))
+        return z, r
+
+    def sap(self, eta, ncy=5, nmr=4, prec="f64", stream=None):
+        nrhs = self._spinor(eta, "eta")
+        psi = self.new_spinor(None if eta.dim() == 6 else nrhs)
+        _lib.check(_lib.load().wc_sap(self._ctx, _ptr(psi), _ptr(eta), nrhs, int(ncy), int(nmr), PREC[prec],
+                                      _stream(stream)))
+        return psi
+
+    def solve(self, b, params: SolverParams | None = None, x0=None, stream=None, check=True, **kw):
+        """x = D^-1 b by SAP-preconditioned FGCR.  Returns (x, list of per-rhs stats dicts)."""
+        nrhs = self._spinor(b, "b")
+        p = params if params is not None else default_params(**kw)
+        if x0 is not None:
+            x = x0.clone()
+            p.x0_given = 1
+        else:
+            x = self.new_spinor(None if b.dim() == 6 else nrhs)
+            p.x0_given = 0
+        st = (SolverStats * nrhs)()
+        rc = _lib.load().wc_fgcr_solve(self._ctx, _ptr(x), _ptr(b), nrhs, ctypes.byref(p), st, _stream(stream))
+        stats = [s.as_dict() for s in st]
+        if check:
+            _lib.check(rc)
+        return x, stats
+
+    def link_grad(self, Y, X, coef=1.0, stream=None):
+        """G with d(sum Re<Y, D X>) = Re sum tr(G^dag dU), times coef (torch gradient convention)."""
+        nrhs = self._spinor(X, "X")
+        self._spinor(Y, "Y")
+        torch = _torch()
+        G = torch.empty_like(self._U)
+        _lib.check(_lib.load().wc_link_grad(self._ctx, _ptr(G), _ptr(Y), _ptr(X), nrhs, float(coef),
+                                            _stream(stream)))
+        return G
+
+    def force(self, phi, params: SolverParams | None = None, stream=None, **kw):
+        """Pseudofermion force of S = phi^dag (D^dag D)^-1 phi; returns (F, Y, X, stats)."""
+        self._spinor(phi, "phi")
+        torch = _torch()
+        p = params if params is not None else default_params(**kw)
+        F = torch.empty_like(self._U)
+        Y = self.new_spinor()
+        X = self.new_spinor()
+        st = (SolverStats * 2)()
+        _lib.check(_lib.load().wc_force(self._ctx, _ptr(F), _ptr(phi), ctypes.byref(p), st, _ptr(Y), _ptr(X),
+                                        _stream(stream)))
+        return F, Y, X, [s.as_dict() for s in st]
+
+    def autotune(self, nrhs, prec="f32", stream=None):
+        out = (ctypes.c_int * 2)()
+        _lib.check(_lib.load().wc_autotune(self._ctx, int(nrhs), PREC[prec], out, _stream(stream)))
+        return int(out[0]), int(out[1])
+
+    def autotune_block(self, params: SolverParams | None = None, stream=None, **kw):
+        p = params if params is not None else default_params(**kw)
+        out = (ctypes.c_int * 4)()
+        _lib.check(_lib.load().wc_autotune_block(self._ctx, ctypes.byref(p), out, _stream(stream)))
+        self.block = tuple(int(v) for v in out)
+        return self.block
+
+    def set_block(self, block, stream=None):
+        blk = (ctypes.c_int * 4)(*block)
+        _lib.check(_lib.load().wc_set_block(self._ctx, blk, _stream(stream)))
+        self.block = tuple(int(b) for b in block)
+
+    def bench_dirac(self, prec="f64", nrhs=1, region="full", iters=50, stream=None):
+        ms = ctypes.c_double()
+        _lib.check(_lib.load().wc_bench_dirac(self._ctx, PREC[prec], int(nrhs), REGION[region], int(iters),
+                                              ctypes.byref(ms), _stream(stream)))
+        return ms.value
+
+    def bench_sap(self, prec="f32", nrhs=1, nmr=4, iters=20, stream=None):
+        ms = ctypes.c_double()
+        _lib.check(_lib.load().wc_bench_sap(self._ctx, PREC[prec], int(nrhs), int(nmr), int(iters), ctypes.byref(ms),
+                                            _stream(stream)))
+        return ms.value
+
+
+def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, check=True, **kw):
+    """Solve several lattices (possibly of different sizes) in one batched solve.
+
+    bs[i] is a complex128 [nrhs_i][dims_i][4][3] tensor.  Returns (xs, stats)."""
+    lib = _lib.load()
+    n = len(lattices)
+    p = params if params is not None else default_params(**kw)
+    p.x0_given = 0
+    xs, nr = [], []
+    for lat, b in zip(lattices, bs):
+        nr.append(lat._spinor(b, "b"))
+        xs.append(lat.new_spinor(None if b.dim() == 6 else nr[-1]))
+    ctxs = (ctypes.c_void_p * n)(*[lat._ctx.value for lat in lattices])
+    xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+    nrhs = (ctypes.c_int * n)(*nr)
+    st = (SolverStats * sum(nr))()
+    rc = lib.wc_fgcr_solve_batch(ctxs, n, xp, bp, nrhs, ctypes.byref(p), st, _stream(stream))
+    if check:
+        _lib.check(rc)
+    return xs, [s.as_dict() for s in st]

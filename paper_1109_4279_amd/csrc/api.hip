@@ -1,0 +1,1071 @@
+// Host side of libwc: contexts, batches of lattices, the FGCR driver and the C interface.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/wc.h"
+#include "wc_kernels.h"
+
+namespace wc {
+
+void launch_force(const int* L, int bc_t, const void* Ucanon, const void* Y, const void* X, int nrhs, double csw,
+                  double coef, int out_kind, void* xi_work, void* out, hipStream_t st);
+void launch_gamma5_canon(long long nsite, const void* src, void* dst, hipStream_t st);
+void launch_clover_export(const Geom& g, const void* c64, void* out, hipStream_t st);
+void launch_fill_hash(long long n, unsigned seed, void* out, hipStream_t st);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+thread_local std::string g_last_error;
+
+#define HIPCK(expr)                                                                                    \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess)                                                                              \
+      throw Error{e_ == hipErrorOutOfMemory ? WC_ERR_OOM : WC_ERR_HIP,                                 \
+                  std::string(#expr) + ": " + hipGetErrorString(e_)};                                  \
+  } while (0)
+
+static void require(bool ok, int code, const std::string& msg) {
+  if (!ok) throw Error{code, msg};
+}
+
+// owning device allocation
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void ensure(size_t bytes) {
+    if (bytes <= n && p) return;
+    release();
+    HIPCK(hipMalloc(&p, bytes ? bytes : 16));
+    n = bytes;
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+static int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+static int persistent_grid(int nitems, int per_cu) {
+  const int cap = device_cus() * per_cu;
+  return std::max(1, std::min(nitems, cap));
+}
+
+static bool valid_block(const int* L, const int* b) {
+  int vol = 1;
+  for (int m = 0; m < 4; ++m) {
+    if (b[m] <= 0 || L[m] % b[m] || (L[m] / b[m]) % 2) return false;
+    vol *= b[m];
+  }
+  return vol <= 256;
+}
+
+static Geom make_geom(const int* L, const int* B, int bc_t) {
+  Geom g;
+  for (int m = 0; m < 4; ++m) {
+    g.L[m] = L[m];
+    g.B[m] = B[m];
+    g.NB[m] = L[m] / B[m];
+  }
+  g.lstr[3] = 1;
+  g.lstr[2] = B[3];
+  g.lstr[1] = B[3] * B[2];
+  g.lstr[0] = B[3] * B[2] * B[1];
+  g.tstr[3] = 1;
+  g.tstr[2] = g.NB[3];
+  g.tstr[1] = g.NB[3] * g.NB[2];
+  g.tstr[0] = g.NB[3] * g.NB[2] * g.NB[1];
+  g.bvol = B[0] * B[1] * B[2] * B[3];
+  g.ntiles = g.NB[0] * g.NB[1] * g.NB[2] * g.NB[3];
+  g.V = L[0] * L[1] * L[2] * L[3];
+  g.bc_t = bc_t;
+  return g;
+}
+
+static size_t spinor_bytes(int prec, long long sites_rhs) { return (size_t)sites_rhs * spinor_site_bytes(prec); }
+static bool is16(int prec) { return prec == P_F16 || prec == P_BF16; }
+
+// A spinor field in a storage precision: data + optional 16-bit scales.
+struct Field {
+  DevBuf d, sc;
+  int prec = -1;
+  long long n = 0;
+  void ensure(int p, long long sites_rhs) {
+    if (prec == p && n >= sites_rhs && d.p) return;
+    d.ensure(spinor_bytes(p, sites_rhs));
+    if (is16(p)) sc.ensure(sizeof(float) * sites_rhs);
+    prec = p;
+    n = sites_rhs;
+  }
+  void* data() const { return d.p; }
+  float* scale() const { return is16(prec) ? sc.as<float>() : nullptr; }
+};
+
+struct Batch;
+
+}  // namespace wc
+
+struct wc_ctx {
+  int dev = 0;
+  wc::Geom g;
+  int dims[4];
+  int block[4];
+  int bc_t = 1;
+  double m0 = 0, csw = 0;
+  bool have_clover = false;
+  wc::DevBuf Ucanon;
+  wc::DevBuf links[4], lscale[4];
+  bool have_links[4] = {false, false, false, false};
+  wc::DevBuf clov[4], cscale[4];
+  bool have_clov[4] = {false, false, false, false};
+  wc::DevBuf tiles[2];
+  int nr_dirac[4] = {0, 0, 0, 0};
+  int nr_sap[4] = {0, 0, 0, 0};
+  std::map<int, std::unique_ptr<wc::Batch>> batches;  // single-lattice batches by nrhs
+  hipStream_t cap = nullptr;                           // capture stream for graphs
+  ~wc_ctx();
+};
+
+namespace wc {
+
+static void ensure_links(wc_ctx* c, int prec, hipStream_t st) {
+  if (c->have_links[prec]) return;
+  c->links[prec].ensure((size_t)c->g.V * link_site_bytes(prec) + (is16(prec) ? 0 : 0));
+  if (is16(prec)) c->lscale[prec].ensure(sizeof(float) * c->g.V);
+  launch_pack_links(prec, c->g, c->Ucanon.p, c->links[prec].p, c->lscale[prec].as<float>(), st);
+  HIPCK(hipGetLastError());
+  c->have_links[prec] = true;
+}
+
+static void ensure_clover(wc_ctx* c, int prec, hipStream_t st) {
+  require(c->have_clover, WC_ERR_STATE, "clover term not created (call wc_create_clover)");
+  if (c->have_clov[prec]) return;
+  c->clov[prec].ensure((size_t)c->g.V * clover_site_bytes(prec));
+  if (is16(prec)) c->cscale[prec].ensure(sizeof(float) * 2 * c->g.V);
+  launch_clover_convert(prec, c->g, c->clov[P_F64].p, c->clov[prec].p, c->cscale[prec].as<float>(), st);
+  HIPCK(hipGetLastError());
+  c->have_clov[prec] = true;
+}
+
+// ---------------------------------------------------------------------------- batches
+
+struct ItemList {
+  DevBuf d;
+  int n = 0;
+};
+
+struct Batch {
+  std::vector<wc_ctx*> lat;
+  std::vector<int> nrhs;
+  int nsys = 0;
+  long long sites_rhs = 0;
+  int total_chunks = 0;
+  int max_bvol = 0;
+  std::vector<LatDesc> h_lats[4];
+  DevBuf d_lats[4];
+  bool have_lats[4] = {false, false, false, false};
+  std::map<int, ItemList> dirac_items;      // by RHS tile
+  std::map<int, ItemList> sap_items[2];     // by RHS tile
+  DevBuf sys_part, sys_nchunks;
+  DevBuf partials;
+  int pw = 2 * NKV_MAX;
+  // solver state
+  Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
+  DevBuf d_chi, d_phi;
+  Field sap_rho, sap_z, sap_psi;
+  DevBuf sys, skip;
+  // apply / bench buffers per precision
+  Field ain[4], aout[4];
+  // captured restart cycle
+  hipGraphExec_t graph = nullptr;
+  std::string graph_key;
+
+  ~Batch() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
+
+  void init(const std::vector<wc_ctx*>& l, const std::vector<int>& n) {
+    lat = l;
+    nrhs = n;
+    nsys = 0;
+    sites_rhs = 0;
+    total_chunks = 0;
+    max_bvol = 0;
+    std::vector<int> h_part, h_nch;
+    for (size_t i = 0; i < lat.size(); ++i) {
+      const Geom& g = lat[i]->g;
+      const int nch = (g.V + WG - 1) / WG;
+      for (int r = 0; r < nrhs[i]; ++r) {
+        h_part.push_back(total_chunks + r * nch);
+        h_nch.push_back(nch);
+      }
+      nsys += nrhs[i];
+      sites_rhs += (long long)nrhs[i] * g.V;
+      total_chunks += nrhs[i] * nch;
+      max_bvol = std::max(max_bvol, g.bvol);
+    }
+    sys_part.ensure(sizeof(int) * nsys);
+    sys_nchunks.ensure(sizeof(int) * nsys);
+    HIPCK(hipMemcpy(sys_part.p, h_part.data(), sizeof(int) * nsys, hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(sys_nchunks.p, h_nch.data(), sizeof(int) * nsys, hipMemcpyHostToDevice));
+    partials.ensure(sizeof(double) * (size_t)total_chunks * pw);
+  }
+
+  const LatDesc* lats(int prec, hipStream_t st) {
+    bool stale = !have_lats[prec];
+    for (auto* c : lat) stale |= !c->have_links[prec] || !c->have_clov[prec];
+    if (!stale) return d_lats[prec].as<LatDesc>();
+    h_lats[prec].clear();
+    long long foff = 0;
+    int sys0 = 0, part0 = 0;
+    for (size_t i = 0; i < lat.size(); ++i) {
+      wc_ctx* c = lat[i];
+      ensure_links(c, prec, st);
+      ensure_clover(c, prec, st);
+      LatDesc L;
+      L.g = c->g;
+      L.gauge = c->links[prec].p;
+      L.gscale = c->lscale[prec].as<float>();
+      L.clov = c->clov[prec].p;
+      L.cscale = c->cscale[prec].as<float>();
+      L.foff = foff;
+      L.nrhs = nrhs[i];
+      L.sys0 = sys0;
+      L.part0 = part0;
+      L.nchunks = (c->g.V + WG - 1) / WG;
+      L.tiles[0] = c->tiles[0].as<int>();
+      L.tiles[1] = c->tiles[1].as<int>();
+      h_lats[prec].push_back(L);
+      foff += (long long)nrhs[i] * c->g.V;
+      sys0 += nrhs[i];
+      part0 += nrhs[i] * L.nchunks;
+    }
+    d_lats[prec].ensure(sizeof(LatDesc) * lat.size());
+    HIPCK(hipMemcpy(d_lats[prec].p, h_lats[prec].data(), sizeof(LatDesc) * lat.size(), hipMemcpyHostToDevice));
+    have_lats[prec] = true;
+    return d_lats[prec].as<LatDesc>();
+  }
+
+  const ItemList& items_dirac(int nr) {
+    auto it = dirac_items.find(nr);
+    if (it != dirac_items.end()) return it->second;
+    std::vector<WorkItem> v;
+    for (size_t i = 0; i < lat.size(); ++i) {
+      const int nch = (lat[i]->g.V + WG - 1) / WG;
+      for (int r0 = 0; r0 < nrhs[i]; r0 += nr)
+        for (int c = 0; c < nch; ++c) v.push_back(WorkItem{(int)i, c, r0, std::min(nr, nrhs[i] - r0)});
+    }
+    ItemList& L = dirac_items[nr];
+    L.d.ensure(sizeof(WorkItem) * v.size());
+    HIPCK(hipMemcpy(L.d.p, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
+    L.n = (int)v.size();
+    return L;
+  }
+
+  const ItemList& items_sap(int colour, int nr) {
+    auto it = sap_items[colour].find(nr);
+    if (it != sap_items[colour].end()) return it->second;
+    std::vector<WorkItem> v;
+    for (size_t i = 0; i < lat.size(); ++i) {
+      const int nt = lat[i]->g.ntiles / 2;
+      for (int r0 = 0; r0 < nrhs[i]; r0 += nr)
+        for (int t = 0; t < nt; ++t) v.push_back(WorkItem{(int)i, t, r0, std::min(nr, nrhs[i] - r0)});
+    }
+    ItemList& L = sap_items[colour][nr];
+    L.d.ensure(sizeof(WorkItem) * v.size());
+    HIPCK(hipMemcpy(L.d.p, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
+    L.n = (int)v.size();
+    return L;
+  }
+
+  int sap_threads() const { return ((max_bvol + 63) / 64) * 64; }
+};
+
+static Batch& ctx_batch(wc_ctx* c, int nrhs) {
+  auto it = c->batches.find(nrhs);
+  if (it != c->batches.end()) return *it->second;
+  auto b = std::make_unique<Batch>();
+  b->init({c}, {nrhs});
+  Batch& ref = *b;
+  c->batches[nrhs] = std::move(b);
+  return ref;
+}
+
+static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
+
+static int default_nr(int nrhs, int prec, bool sap) {
+  if (nrhs <= 1) return 1;
+  if (sap) return prec == P_F64 ? 1 : 2;
+  return nrhs >= 4 ? 4 : nrhs;
+}
+
+static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested) {
+  int nr = requested > 0 ? requested : (sap ? c->nr_sap[prec] : c->nr_dirac[prec]);
+  if (nr <= 0) nr = default_nr(nrhs, prec, sap);
+  nr = std::min(nr, 4);
+  // block-solver tiles keep the LDS exchange buffer within 64 KB: FP64 one rhs, else two
+  if (sap) nr = std::min(nr, prec == P_F64 ? 1 : 2);
+  return std::max(1, std::min(nr, std::max(1, nrhs)));
+}
+
+// ---------------------------------------------------------------------------- kernels on a batch
+
+static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, const Field* y, double* partials,
+                      const int* skip, int dagger, int block, hipStream_t st) {
+  const LatDesc* L = B.lats(prec, st);
+  const ItemList& it = B.items_dirac(nr);
+  DiracLaunch a;
+  a.lats = L;
+  a.items = it.d.as<WorkItem>();
+  a.nitems = it.n;
+  a.in = in.data();
+  a.in_sc = in.scale();
+  a.out = out.data();
+  a.out_sc = out.scale();
+  a.y = y ? y->data() : nullptr;
+  a.y_sc = y ? y->scale() : nullptr;
+  a.partials = partials;
+  a.pw = B.pw;
+  a.skip = skip;
+  a.dagger = dagger;
+  a.block = block;
+  launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
+}
+
+static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
+                              const int* skip, int first, int border, int wrho, int wz, hipStream_t st) {
+  require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
+  require(sap_lds_bytes(prec, nr, B.sap_threads()) <= 65536, WC_ERR_GEOMETRY, "block too large for LDS");
+  const LatDesc* L = B.lats(prec, st);
+  const ItemList& it = B.items_sap(colour, nr);
+  SapLaunch a;
+  a.lats = L;
+  a.items = it.d.as<WorkItem>();
+  a.nitems = it.n;
+  a.colour = colour;
+  a.nmr = nmr;
+  a.rho = rho.data();
+  a.rho_sc = rho.scale();
+  a.z = z.data();
+  a.z_sc = z.scale();
+  a.psi = psi.data();
+  a.psi_sc = psi.scale();
+  a.skip = skip;
+  a.first = first;
+  a.border = border;
+  a.write_rho = wrho;
+  a.write_z = wz;
+  launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), B.sap_threads(), st);
+}
+
+// ncy Schwarz cycles on rho (source), accumulating psi
+static void run_sap(Batch& B, int prec, int nr, int ncy, int nmr, Field& rho, Field& z, Field& psi, const int* skip,
+                    hipStream_t st) {
+  for (int cy = 0; cy < ncy; ++cy)
+    for (int c = 0; c < 2; ++c) {
+      const bool last = (cy == ncy - 1);
+      run_sap_halfsweep(B, prec, nr, c, nmr, rho, z, psi, skip, cy == 0, !(cy == 0 && c == 0), !last,
+                        !(last && c == 1), st);
+    }
+}
+
+// pack / unpack canonical arrays of every lattice of the batch
+static void pack_batch(Batch& B, int prec, const void* const* canon, Field& f, hipStream_t st) {
+  long long off = 0;
+  for (size_t i = 0; i < B.lat.size(); ++i) {
+    const Geom& g = B.lat[i]->g;
+    launch_pack_spinor(prec, g, B.nrhs[i], canon[i], (char*)f.data() + off * spinor_site_bytes(prec),
+                       f.scale() ? f.scale() + off : nullptr, st);
+    off += (long long)B.nrhs[i] * g.V;
+  }
+}
+static void unpack_batch(Batch& B, int prec, const Field& f, void* const* canon, int colour_only, hipStream_t st) {
+  long long off = 0;
+  for (size_t i = 0; i < B.lat.size(); ++i) {
+    const Geom& g = B.lat[i]->g;
+    launch_unpack_spinor(prec, g, B.nrhs[i], (const char*)f.data() + off * spinor_site_bytes(prec),
+                         f.scale() ? f.scale() + off : nullptr, canon[i], colour_only, st);
+    off += (long long)B.nrhs[i] * g.V;
+  }
+}
+
+// ---------------------------------------------------------------------------- FGCR
+
+struct SolveSetup {
+  int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit;
+  double tol;
+};
+
+static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
+  VecLaunch a;
+  a.lats = B.lats(P_F64, st);
+  const ItemList& it = B.items_dirac(1);
+  a.items = it.d.as<WorkItem>();
+  a.nitems = it.n;
+  a.sys = B.sys.as<SysState>();
+  a.skip = B.skip.as<int>();
+  a.partials = B.partials.as<double>();
+  a.pw = B.pw;
+  a.k = 0;
+  a.maxit = s.maxit;
+  a.tol = s.tol;
+  a.r = B.r.d.as<double2>();
+  a.x = B.x.d.as<double2>();
+  a.chi = B.d_chi.as<double2* const>();
+  a.phi = B.d_phi.as<double2* const>();
+  a.sp = nullptr;
+  a.sp_sc = nullptr;
+  return a;
+}
+
+static void prepare_solver(Batch& B, const SolveSetup& s) {
+  const long long n = B.sites_rhs;
+  B.x.ensure(P_F64, n);
+  B.b.ensure(P_F64, n);
+  B.r.ensure(P_F64, n);
+  std::vector<double2*> pc(NKV_MAX, nullptr), pp(NKV_MAX, nullptr);
+  for (int k = 0; k < s.nkv; ++k) {
+    B.chi[k].ensure(P_F64, n);
+    B.phi[k].ensure(P_F64, n);
+    pc[k] = B.chi[k].d.as<double2>();
+    pp[k] = B.phi[k].d.as<double2>();
+  }
+  B.d_chi.ensure(sizeof(double2*) * NKV_MAX);
+  B.d_phi.ensure(sizeof(double2*) * NKV_MAX);
+  HIPCK(hipMemcpy(B.d_chi.p, pc.data(), sizeof(double2*) * NKV_MAX, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(B.d_phi.p, pp.data(), sizeof(double2*) * NKV_MAX, hipMemcpyHostToDevice));
+  B.sap_rho.ensure(s.sap_prec, n);
+  B.sap_z.ensure(s.sap_prec, n);
+  B.sap_psi.ensure(s.sap_prec, n);
+  B.sys.ensure(sizeof(SysState) * B.nsys);
+  B.skip.ensure(sizeof(int) * B.nsys);
+  // everything a captured cycle touches must exist before capture starts
+  B.lats(P_F64, nullptr);
+  B.lats(s.sap_prec, nullptr);
+  B.items_dirac(1);
+  B.items_dirac(s.nr_d);
+  B.items_sap(0, s.nr_s);
+  B.items_sap(1, s.nr_s);
+  HIPCK(hipDeviceSynchronize());
+}
+
+// one restart cycle: nkv FGCR iterations; systems whose skip flag is set sit out
+static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
+  VecLaunch va = vec_launch(B, s, st);
+  const int gv = persistent_grid(va.nitems, 8);
+  const int* skip = B.skip.as<int>();
+  for (int k = 0; k < s.nkv; ++k) {
+    va.k = k;
+    // phi_k = |r| M_SAP(r / |r|)
+    VecLaunch vs = va;
+    vs.sp = B.sap_rho.data();
+    vs.sp_sc = B.sap_rho.scale();
+    launch_to_sap(s.sap_prec, vs, gv, st);
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.sap_psi, skip, st);
+    vs.sp = B.sap_psi.data();
+    vs.sp_sc = B.sap_psi.scale();
+    launch_from_sap(s.sap_prec, vs, gv, st);
+    // chi_k = D phi_k in FP64
+    run_dirac(B, P_F64, s.nr_d, B.phi[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
+    if (k > 0) {
+      launch_multidot(va, gv, st);
+      launch_reduce(RED_MULTIDOT, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+    }
+    launch_gs_update(va, gv, st);
+    launch_reduce(RED_GS, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+    launch_update_r(va, gv, st);
+    launch_reduce(RED_RNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  }
+  // x += sum alpha phi; r = b - D x in FP64
+  launch_backsub(va, B.nsys, st);
+  launch_x_update(va, gv, st);
+  run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+  launch_reduce(RED_TRUE, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+}
+
+static std::string setup_key(const SolveSetup& s) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s, s.maxit,
+           s.tol);
+  return buf;
+}
+
+static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_graph, wc_ctx* cap_owner,
+                      std::vector<wc_solver_stats>& stats, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  HIPCK(hipEventRecord(e0, st));
+  VecLaunch va = vec_launch(B, s, st);
+  const int gv = persistent_grid(va.nitems, 8);
+  // |b|^2 -> tolerance; r = b (x = 0) or r = b - D x0
+  launch_norm2(va, B.b.d.as<double2>(), gv, st);
+  launch_reduce(RED_BNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  if (x0_given) {
+    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    launch_reduce(RED_INITR, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  } else {
+    HIPCK(hipMemsetAsync(B.x.data(), 0, spinor_bytes(P_F64, B.sites_rhs), st));
+    launch_copy_f64(va, B.r.d.as<double2>(), B.b.d.as<double2>(), gv, st);
+  }
+  HIPCK(hipGetLastError());
+
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const std::string key = setup_key(s);
+    if (B.graph && B.graph_key == key) {
+      exec = B.graph;
+    } else {
+      if (B.graph) {
+        HIPCK(hipGraphExecDestroy(B.graph));
+        B.graph = nullptr;
+      }
+      if (!cap_owner->cap) HIPCK(hipStreamCreateWithFlags(&cap_owner->cap, hipStreamNonBlocking));
+      hipGraph_t graph;
+      HIPCK(hipStreamBeginCapture(cap_owner->cap, hipStreamCaptureModeThreadLocal));
+      enqueue_cycle(B, s, cap_owner->cap);
+      HIPCK(hipStreamEndCapture(cap_owner->cap, &graph));
+      HIPCK(hipGraphInstantiate(&B.graph, graph, nullptr, nullptr, 0));
+      HIPCK(hipGraphDestroy(graph));
+      B.graph_key = key;
+      exec = B.graph;
+    }
+  }
+
+  std::vector<int> h_skip(B.nsys);
+  const int max_restarts = s.maxit + 1;
+  for (int rs = 0; rs < max_restarts; ++rs) {
+    HIPCK(hipMemcpyAsync(h_skip.data(), B.skip.p, sizeof(int) * B.nsys, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    bool all = true;
+    for (int v : h_skip) all &= (v != 0);
+    if (all) break;
+    if (exec)
+      HIPCK(hipGraphLaunch(exec, st));
+    else
+      enqueue_cycle(B, s, st);
+    HIPCK(hipGetLastError());
+  }
+  HIPCK(hipEventRecord(e1, st));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+
+  std::vector<SysState> hs(B.nsys);
+  HIPCK(hipMemcpy(hs.data(), B.sys.p, sizeof(SysState) * B.nsys, hipMemcpyDeviceToHost));
+  int rc = WC_OK;
+  stats.resize(B.nsys);
+  for (int i = 0; i < B.nsys; ++i) {
+    wc_solver_stats& o = stats[i];
+    const SysState& S = hs[i];
+    o.iters = S.iters;
+    o.restarts = S.restarts;
+    o.breakdown = S.breakdown;
+    o.rel_true_res = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+    o.time_ms = ms;
+    if (S.breakdown)
+      o.status = WC_ERR_BREAKDOWN;
+    else if (S.bnorm2 > 0 && !(S.rnorm2 <= S.tol2))
+      o.status = WC_ERR_NOT_CONVERGED;
+    else
+      o.status = WC_OK;
+    if (rc == WC_OK && o.status != WC_OK) rc = o.status;
+  }
+  return rc;
+}
+
+static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs) {
+  require(p.nkv >= 1 && p.nkv <= NKV_MAX, WC_ERR_ARG, "nkv must be in 1..32");
+  require(p.ncy >= 1 && p.nmr >= 1, WC_ERR_ARG, "ncy and nmr must be >= 1");
+  require(p.sap_prec >= 0 && p.sap_prec <= 3, WC_ERR_ARG, "bad sap_prec");
+  require(p.tol > 0 && p.maxit >= 1, WC_ERR_ARG, "tol must be > 0 and maxit >= 1");
+  SolveSetup s;
+  s.nkv = p.nkv;
+  s.ncy = p.ncy;
+  s.nmr = p.nmr;
+  s.sap_prec = p.sap_prec;
+  s.tol = p.tol;
+  s.maxit = p.maxit;
+  s.nr_d = pick_nr(c, max_nrhs, P_F64, false, p.nr_dirac);
+  s.nr_s = pick_nr(c, max_nrhs, p.sap_prec, true, p.nr_sap);
+  return s;
+}
+
+// ---------------------------------------------------------------------------- helpers for the C interface
+
+static hipStream_t S(void* stream) { return (hipStream_t)stream; }
+
+template <class F> static int guarded(F f) {
+  try {
+    f();
+    return WC_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return WC_ERR_OOM;
+  } catch (...) {
+    g_last_error = "unexpected error";
+    return WC_ERR_HIP;
+  }
+}
+
+static void check_prec(int prec) { require(prec >= 0 && prec <= 3, WC_ERR_ARG, "bad precision"); }
+
+static void layout(wc_ctx* c, const int* block, hipStream_t st) {
+  require(valid_block(c->dims, block), WC_ERR_GEOMETRY,
+          "block must divide the lattice into an even number of blocks along every axis, <= 256 sites");
+  invalidate_batches(c);
+  for (int m = 0; m < 4; ++m) c->block[m] = block[m];
+  c->g = make_geom(c->dims, block, c->bc_t);
+  std::vector<int> t0, t1;
+  for (int t = 0; t < c->g.ntiles; ++t) {
+    int tc[4];
+    tile_coords(c->g, t, tc);
+    (tile_colour(tc) ? t1 : t0).push_back(t);
+  }
+  c->tiles[0].ensure(sizeof(int) * t0.size());
+  c->tiles[1].ensure(sizeof(int) * t1.size());
+  HIPCK(hipMemcpy(c->tiles[0].p, t0.data(), sizeof(int) * t0.size(), hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(c->tiles[1].p, t1.data(), sizeof(int) * t1.size(), hipMemcpyHostToDevice));
+  for (int p = 0; p < 4; ++p) {
+    c->have_links[p] = false;
+    c->have_clov[p] = false;
+  }
+  ensure_links(c, P_F64, st);
+  if (c->have_clover) {
+    c->clov[P_F64].ensure((size_t)c->g.V * clover_site_bytes(P_F64));
+    launch_clover_build(c->g, c->links[P_F64].p, c->m0, c->csw, c->clov[P_F64].p, st);
+    HIPCK(hipGetLastError());
+    c->have_clov[P_F64] = true;
+  }
+}
+
+}  // namespace wc
+
+wc_ctx::~wc_ctx() {
+  batches.clear();
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
+using namespace wc;
+
+extern "C" {
+
+void wc_default_params(wc_solver_params* p) {
+  if (!p) return;
+  p->nkv = 16;
+  p->ncy = 5;
+  p->nmr = 4;
+  p->sap_prec = WC_F32;
+  p->tol = 1e-10;
+  p->maxit = 10000;
+  p->x0_given = 0;
+  p->use_graph = 1;
+  p->nr_dirac = 0;
+  p->nr_sap = 0;
+}
+
+int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const void* U, int bc_t, void* stream) {
+  return guarded([&] {
+    require(ctx && dims && block && U, WC_ERR_ARG, "null argument");
+    require(bc_t == 1 || bc_t == -1, WC_ERR_ARG, "bc_t must be +1 or -1");
+    for (int m = 0; m < 4; ++m) require(dims[m] >= 2, WC_ERR_GEOMETRY, "lattice extents must be >= 2");
+    auto c = std::make_unique<wc_ctx>();
+    HIPCK(hipGetDevice(&c->dev));
+    for (int m = 0; m < 4; ++m) c->dims[m] = dims[m];
+    c->bc_t = bc_t;
+    const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    require(V < (1LL << 30), WC_ERR_GEOMETRY, "lattice too large");
+    c->Ucanon.ensure((size_t)V * 4 * 9 * 16);
+    HIPCK(hipMemcpyAsync(c->Ucanon.p, U, (size_t)V * 4 * 9 * 16, hipMemcpyDeviceToDevice, S(stream)));
+    layout(c.get(), block, S(stream));
+    HIPCK(hipStreamSynchronize(S(stream)));
+    *ctx = c.release();
+  });
+}
+
+int wc_create_clover(wc_ctx* c, double m0, double csw, void* stream) {
+  return guarded([&] {
+    require(c, WC_ERR_ARG, "null context");
+    c->m0 = m0;
+    c->csw = csw;
+    c->clov[P_F64].ensure((size_t)c->g.V * clover_site_bytes(P_F64));
+    launch_clover_build(c->g, c->links[P_F64].p, m0, csw, c->clov[P_F64].p, S(stream));
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(S(stream)));
+    c->have_clover = true;
+    for (int p = 0; p < 4; ++p) c->have_clov[p] = (p == P_F64);
+    for (auto& kv : c->batches)
+      for (int p = 0; p < 4; ++p) kv.second->have_lats[p] = false;
+  });
+}
+
+int wc_set_block(wc_ctx* c, const int block[4], void* stream) {
+  return guarded([&] {
+    require(c && block, WC_ERR_ARG, "null argument");
+    layout(c, block, S(stream));
+  });
+}
+
+int wc_clover_export(wc_ctx* c, void* A, void* stream) {
+  return guarded([&] {
+    require(c && A, WC_ERR_ARG, "null argument");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    launch_clover_export(c->g, c->clov[P_F64].p, A, S(stream));
+    HIPCK(hipGetLastError());
+  });
+}
+
+int wc_apply_D(wc_ctx* c, void* out, const void* in, int nrhs, int prec, int region, int dagger, void* stream) {
+  return guarded([&] {
+    require(c && out && in && nrhs >= 1, WC_ERR_ARG, "null argument or nrhs < 1");
+    check_prec(prec);
+    require(region == WC_FULL || region == WC_BLOCKS, WC_ERR_ARG, "bad region");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    Batch& B = ctx_batch(c, nrhs);
+    B.ain[prec].ensure(prec, B.sites_rhs);
+    B.aout[prec].ensure(prec, B.sites_rhs);
+    const void* ins[1] = {in};
+    void* outs[1] = {out};
+    pack_batch(B, prec, ins, B.ain[prec], st);
+    run_dirac(B, prec, pick_nr(c, nrhs, prec, false, 0), B.ain[prec], B.aout[prec], nullptr, nullptr, nullptr,
+              dagger ? 1 : 0, region == WC_BLOCKS, st);
+    unpack_batch(B, prec, B.aout[prec], outs, -1, st);
+    HIPCK(hipGetLastError());
+  });
+}
+
+int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr, int prec, void* stream) {
+  return guarded([&] {
+    require(c && z && rho && nrhs >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    require(colour == 0 || colour == 1, WC_ERR_ARG, "colour must be 0 or 1");
+    check_prec(prec);
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    Batch& B = ctx_batch(c, nrhs);
+    B.sap_rho.ensure(prec, B.sites_rhs);
+    B.sap_z.ensure(prec, B.sites_rhs);
+    B.sap_psi.ensure(prec, B.sites_rhs);
+    const void* ins[1] = {rho};
+    pack_batch(B, prec, ins, B.sap_rho, st);
+    run_sap_halfsweep(B, prec, pick_nr(c, nrhs, prec, true, 0), colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr,
+                      1, 0, 1, 1, st);
+    void* zo[1] = {z};
+    void* ro[1] = {rho};
+    unpack_batch(B, prec, B.sap_z, zo, colour, st);
+    unpack_batch(B, prec, B.sap_rho, ro, colour, st);
+    HIPCK(hipGetLastError());
+  });
+}
+
+int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, void* stream) {
+  return guarded([&] {
+    require(c && psi && eta && nrhs >= 1 && ncy >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    check_prec(prec);
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    Batch& B = ctx_batch(c, nrhs);
+    B.sap_rho.ensure(prec, B.sites_rhs);
+    B.sap_z.ensure(prec, B.sites_rhs);
+    B.sap_psi.ensure(prec, B.sites_rhs);
+    const void* ins[1] = {eta};
+    pack_batch(B, prec, ins, B.sap_rho, st);
+    run_sap(B, prec, pick_nr(c, nrhs, prec, true, 0), ncy, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, st);
+    void* outs[1] = {psi};
+    unpack_batch(B, prec, B.sap_psi, outs, -1, st);
+    HIPCK(hipGetLastError());
+  });
+}
+
+static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<int>& nrhs, void* const* x,
+                            const void* const* b, const wc_solver_params* p, wc_solver_stats* st_out, void* stream,
+                            Batch* cached) {
+  int rc = WC_OK;
+  int grc = guarded([&] {
+    require(p, WC_ERR_ARG, "null params");
+    int max_nrhs = 0;
+    for (size_t i = 0; i < ctxs.size(); ++i) {
+      require(ctxs[i] && x[i] && b[i] && nrhs[i] >= 1, WC_ERR_ARG, "bad lattice argument");
+      require(ctxs[i]->have_clover, WC_ERR_STATE, "clover term not created");
+      max_nrhs = std::max(max_nrhs, nrhs[i]);
+    }
+    hipStream_t st = S(stream);
+    std::unique_ptr<Batch> owned;
+    Batch* B = cached;
+    if (!B) {
+      owned = std::make_unique<Batch>();
+      owned->init(ctxs, nrhs);
+      B = owned.get();
+    }
+    SolveSetup s = make_setup(*p, ctxs[0], max_nrhs);
+    prepare_solver(*B, s);
+    pack_batch(*B, P_F64, b, B->b, st);
+    if (p->x0_given) pack_batch(*B, P_F64, (const void* const*)x, B->x, st);
+    std::vector<wc_solver_stats> stats;
+    rc = fgcr_solve(*B, s, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
+    unpack_batch(*B, P_F64, B->x, x, -1, st);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(st));
+    if (st_out)
+      for (size_t i = 0; i < stats.size(); ++i) st_out[i] = stats[i];
+    if (rc != WC_OK) g_last_error = rc == WC_ERR_BREAKDOWN ? "FGCR breakdown" : "FGCR did not converge within maxit";
+  });
+  return grc != WC_OK ? grc : rc;
+}
+
+int wc_fgcr_solve(wc_ctx* c, void* x, const void* b, int nrhs, const wc_solver_params* p, wc_solver_stats* st,
+                  void* stream) {
+  if (!c || nrhs < 1) {
+    g_last_error = "null context or nrhs < 1";
+    return WC_ERR_ARG;
+  }
+  Batch* B = nullptr;
+  int rc = guarded([&] { B = &ctx_batch(c, nrhs); });
+  if (rc != WC_OK) return rc;
+  void* xs[1] = {x};
+  const void* bs[1] = {b};
+  return solve_batch_impl({c}, {nrhs}, xs, bs, p, st, stream, B);
+}
+
+int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
+                        const wc_solver_params* p, wc_solver_stats* st, void* stream) {
+  if (!ctxs || nlat < 1 || !x || !b || !nrhs) {
+    g_last_error = "null argument";
+    return WC_ERR_ARG;
+  }
+  std::vector<wc_ctx*> cs(ctxs, ctxs + nlat);
+  std::vector<int> ns(nrhs, nrhs + nlat);
+  return solve_batch_impl(cs, ns, x, b, p, st, stream, nullptr);
+}
+
+int wc_link_grad(wc_ctx* c, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream) {
+  return guarded([&] {
+    require(c && G && Y && X && nrhs >= 1, WC_ERR_ARG, "bad argument");
+    DevBuf xi;
+    if (c->csw != 0.0) xi.ensure(sizeof(double2) * 54 * (size_t)c->g.V);
+    launch_force(c->dims, c->bc_t, c->Ucanon.p, Y, X, nrhs, c->have_clover ? c->csw : 0.0, coef, 0, xi.p, G,
+                 S(stream));
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_solver_stats* st, void* Yout,
+             void* Xout, void* stream) {
+  int rc_solve = WC_OK;
+  int rc = guarded([&] {
+    require(c && F && phi && p, WC_ERR_ARG, "bad argument");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st_ = S(stream);
+    const size_t bytes = (size_t)c->g.V * 192;
+    DevBuf y, x, tmp;
+    y.ensure(bytes);
+    x.ensure(bytes);
+    tmp.ensure(bytes);
+    // Y = D^-dag phi = g5 D^-1 g5 phi (gamma5-hermiticity), then X = D^-1 Y
+    wc_solver_params q = *p;
+    q.x0_given = 0;
+    wc_solver_stats s2[2];
+    launch_gamma5_canon(c->g.V, phi, tmp.p, st_);
+    int r1 = wc_fgcr_solve(c, y.p, tmp.p, 1, &q, &s2[0], stream);
+    require(r1 == WC_OK || r1 == WC_ERR_NOT_CONVERGED || r1 == WC_ERR_BREAKDOWN, r1, g_last_error);
+    launch_gamma5_canon(c->g.V, y.p, y.p, st_);
+    int r2 = wc_fgcr_solve(c, x.p, y.p, 1, &q, &s2[1], stream);
+    require(r2 == WC_OK || r2 == WC_ERR_NOT_CONVERGED || r2 == WC_ERR_BREAKDOWN, r2, g_last_error);
+    rc_solve = r1 != WC_OK ? r1 : r2;
+    DevBuf xi;
+    if (c->csw != 0.0) xi.ensure(sizeof(double2) * 54 * (size_t)c->g.V);
+    launch_force(c->dims, c->bc_t, c->Ucanon.p, y.p, x.p, 1, c->csw, 1.0, 1, xi.p, F, st_);
+    HIPCK(hipGetLastError());
+    if (Yout) HIPCK(hipMemcpyAsync(Yout, y.p, bytes, hipMemcpyDeviceToDevice, st_));
+    if (Xout) HIPCK(hipMemcpyAsync(Xout, x.p, bytes, hipMemcpyDeviceToDevice, st_));
+    HIPCK(hipStreamSynchronize(st_));
+    if (st) {
+      st[0] = s2[0];
+      st[1] = s2[1];
+    }
+  });
+  return rc != WC_OK ? rc : rc_solve;
+}
+
+static double time_launches(hipStream_t st, int iters, const std::function<void()>& f) {
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  f();  // warm-up
+  HIPCK(hipEventRecord(e0, st));
+  for (int i = 0; i < iters; ++i) f();
+  HIPCK(hipEventRecord(e1, st));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return double(ms) / iters;
+}
+
+int wc_bench_dirac(wc_ctx* c, int prec, int nrhs, int region, int iters, double* ms, void* stream) {
+  return guarded([&] {
+    require(c && ms && nrhs >= 1 && iters >= 1, WC_ERR_ARG, "bad argument");
+    check_prec(prec);
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    Batch& B = ctx_batch(c, nrhs);
+    B.ain[prec].ensure(prec, B.sites_rhs);
+    B.aout[prec].ensure(prec, B.sites_rhs);
+    HIPCK(hipMemsetAsync(B.ain[prec].data(), 0, spinor_bytes(prec, B.sites_rhs), st));
+    if (B.ain[prec].scale()) HIPCK(hipMemsetAsync(B.ain[prec].scale(), 0, sizeof(float) * B.sites_rhs, st));
+    const int nr = pick_nr(c, nrhs, prec, false, 0);
+    *ms = time_launches(st, iters, [&] {
+      run_dirac(B, prec, nr, B.ain[prec], B.aout[prec], nullptr, nullptr, nullptr, 0, region == WC_BLOCKS, st);
+    });
+    HIPCK(hipGetLastError());
+  });
+}
+
+int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int iters, double* ms, void* stream) {
+  return guarded([&] {
+    require(c && ms && nrhs >= 1 && iters >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    check_prec(prec);
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    Batch& B = ctx_batch(c, nrhs);
+    B.sap_rho.ensure(prec, B.sites_rhs);
+    B.sap_z.ensure(prec, B.sites_rhs);
+    B.sap_psi.ensure(prec, B.sites_rhs);
+    HIPCK(hipMemsetAsync(B.sap_rho.data(), 0, spinor_bytes(prec, B.sites_rhs), st));
+    HIPCK(hipMemsetAsync(B.sap_z.data(), 0, spinor_bytes(prec, B.sites_rhs), st));
+    if (B.sap_rho.scale()) {
+      HIPCK(hipMemsetAsync(B.sap_rho.scale(), 0, sizeof(float) * B.sites_rhs, st));
+      HIPCK(hipMemsetAsync(B.sap_z.scale(), 0, sizeof(float) * B.sites_rhs, st));
+    }
+    const int nr = pick_nr(c, nrhs, prec, true, 0);
+    int colour = 0;
+    *ms = time_launches(st, iters, [&] {
+      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, st);
+      colour ^= 1;
+    });
+    HIPCK(hipGetLastError());
+  });
+}
+
+int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[2], void* stream) {
+  return guarded([&] {
+    require(c && nrhs >= 1, WC_ERR_ARG, "bad argument");
+    check_prec(prec);
+    const int cands[3] = {1, 2, 4};
+    double best_d = 1e30, best_s = 1e30;
+    int nd = 1, ns = 1;
+    for (int nr : cands) {
+      if (nr > nrhs) continue;
+      c->nr_dirac[prec] = nr;
+      double t = 0;
+      int rc = wc_bench_dirac(c, prec, nrhs, WC_FULL, 20, &t, stream);
+      require(rc == WC_OK, rc, g_last_error);
+      if (t < best_d) { best_d = t; nd = nr; }
+      if (nr > (prec == P_F64 ? 1 : 2)) continue;
+      c->nr_sap[prec] = nr;
+      rc = wc_bench_sap(c, prec, nrhs, 4, 10, &t, stream);
+      require(rc == WC_OK, rc, g_last_error);
+      if (t < best_s) { best_s = t; ns = nr; }
+    }
+    c->nr_dirac[prec] = nd;
+    c->nr_sap[prec] = ns;
+    if (nr_out) {
+      nr_out[0] = nd;
+      nr_out[1] = ns;
+    }
+  });
+}
+
+int wc_autotune_block(wc_ctx* c, const wc_solver_params* p, int block_out[4], void* stream) {
+  return guarded([&] {
+    require(c && p, WC_ERR_ARG, "bad argument");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st = S(stream);
+    // candidate shapes: every axis a divisor b of L with an even block count, b <= 8,
+    // 16 <= volume <= 256
+    std::vector<std::array<int, 4>> cands;
+    std::vector<int> divs[4];
+    for (int m = 0; m < 4; ++m)
+      for (int b = 1; b <= 8; ++b)
+        if (c->dims[m] % b == 0 && (c->dims[m] / b) % 2 == 0) divs[m].push_back(b);
+    for (int b0 : divs[0])
+      for (int b1 : divs[1])
+        for (int b2 : divs[2])
+          for (int b3 : divs[3]) {
+            const int vol = b0 * b1 * b2 * b3;
+            // keep near-isotropic shapes (spatial extents equal, time extent within 2x)
+            if (vol < 16 || vol > 256 || b1 != b2 || b2 != b3 || b0 > 2 * b1 || b1 > 2 * b0) continue;
+            cands.push_back({b0, b1, b2, b3});
+          }
+    require(!cands.empty(), WC_ERR_GEOMETRY, "no valid block shape for this lattice");
+    const size_t bytes = (size_t)c->g.V * 192;
+    DevBuf bsrc, xsol;
+    bsrc.ensure(bytes);
+    xsol.ensure(bytes);
+    launch_fill_hash((long long)c->g.V * 12, 12345u, bsrc.p, st);
+    HIPCK(hipGetLastError());
+    double best = 1e300;
+    std::array<int, 4> best_b = {c->block[0], c->block[1], c->block[2], c->block[3]};
+    for (auto& b : cands) {
+      layout(c, b.data(), st);
+      wc_solver_params q = *p;
+      q.x0_given = 0;
+      wc_solver_stats sst;
+      // first solve builds graphs and buffers; the second is timed
+      int rc = wc_fgcr_solve(c, xsol.p, bsrc.p, 1, &q, &sst, stream);
+      if (rc != WC_OK && rc != WC_ERR_NOT_CONVERGED) continue;
+      rc = wc_fgcr_solve(c, xsol.p, bsrc.p, 1, &q, &sst, stream);
+      if (rc != WC_OK) continue;
+      if (sst.time_ms < best) {
+        best = sst.time_ms;
+        best_b = b;
+      }
+    }
+    layout(c, best_b.data(), st);
+    if (block_out)
+      for (int m = 0; m < 4; ++m) block_out[m] = best_b[m];
+  });
+}
+
+const char* wc_last_error(void) { return g_last_error.c_str(); }
+
+int wc_version(void) { return 100; }
+
+void wc_destroy(wc_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,0 +1,386 @@
+// FP64 vector kernels of the restarted FGCR outer solver (arXiv:1109.4279, Sec. 4):
+// Gram-Schmidt against the previous directions, residual update, solution update,
+// and the conversions to and from the Schwarz preconditioner's precision.
+//
+// Every kernel walks (lattice, system, 256-site chunk) work items; per-system scalars
+// live in device memory (SysState) so a whole restart cycle runs without the host.
+// Reductions are deterministic: per-chunk partial sums, then one work-group per
+// system adds them in a fixed order.
+#include "wc_kernels.h"
+
+namespace wc {
+
+struct VecSite {
+  int sys;
+  int s;
+  bool valid;
+  long long off;  // site*rhs offset of this system's field
+  int part;       // partial index of this (system, chunk)
+  int V;
+};
+
+WC_D VecSite vec_site(const VecLaunch& a, int it0) {
+  const WorkItem w = a.items[xcd_remap(it0, a.nitems)];
+  const LatDesc& L = a.lats[w.lat];
+  VecSite v;
+  v.sys = L.sys0 + w.rhs0;
+  v.s = w.chunk * WG + threadIdx.x;
+  v.V = L.g.V;
+  v.valid = v.s < v.V;
+  if (!v.valid) v.s = v.V - 1;
+  v.off = L.foff + (long long)w.rhs0 * v.V;
+  v.part = L.part0 + w.rhs0 * L.nchunks + w.chunk;
+  return v;
+}
+
+WC_D Spinor<double> ld64(const double2* base, const VecSite& v) {
+  return SpinorIO<P_F64>::load(FieldRef{(void*)(base + v.off * 12), nullptr, v.V}, v.s);
+}
+WC_D void st64(double2* base, const VecSite& v, const Spinor<double>& p) {
+  SpinorIO<P_F64>::store(FieldRef{(void*)(base + v.off * 12), nullptr, v.V}, v.s, p);
+}
+
+// reduce NV values of the work-group and store them as this chunk's partial
+template <int NV> WC_D void put_partial(const VecLaunch& a, const VecSite& v, double* vals, double* lds) {
+  block_sum<NV>(vals, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a.partials[(size_t)v.part * a.pw + i] = vals[i];
+  }
+}
+
+// ------------------------------------------------------------------ conversions
+
+template <int P>
+__global__ __launch_bounds__(WG) void k_to_sap(VecLaunch a) {
+  typedef typename Real<P>::T R;
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys] || !v.valid) continue;
+    const double inv = 1.0 / sqrt(a.sys[v.sys].rnorm2);
+    Spinor<double> r = ld64(a.r, v);
+    Spinor<R> o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o.c[i][c] = {R(r.c[i][c].re * inv), R(r.c[i][c].im * inv)};
+    SpinorIO<P>::store(FieldRef{(char*)a.sp + v.off * spinor_site_bytes(P), a.sp_sc ? a.sp_sc + v.off : nullptr, v.V},
+                       v.s, o);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(WG) void k_from_sap(VecLaunch a) {
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys] || !v.valid) continue;
+    const double sc = sqrt(a.sys[v.sys].rnorm2);
+    auto p = SpinorIO<P>::load(
+        FieldRef{(char*)a.sp + v.off * spinor_site_bytes(P), a.sp_sc ? a.sp_sc + v.off : nullptr, v.V}, v.s);
+    Spinor<double> o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o.c[i][c] = {sc * double(p.c[i][c].re), sc * double(p.c[i][c].im)};
+    st64(a.phi[a.k], v, o);
+  }
+}
+
+// ------------------------------------------------------------------ Gram-Schmidt
+
+__global__ __launch_bounds__(WG) void k_multidot(VecLaunch a) {
+  __shared__ double lds[(WG / 64) * 2 * NKV_MAX];
+  const int k = a.k;
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys]) continue;
+    Spinor<double> ck = ld64(a.chi[k], v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int l = 0; l < k; ++l) {
+      Spinor<double> cl = ld64(a.chi[l], v);
+      double re = 0.0, im = 0.0;
+      if (v.valid) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            re += cl.c[i][c].re * ck.c[i][c].re + cl.c[i][c].im * ck.c[i][c].im;
+            im += cl.c[i][c].re * ck.c[i][c].im - cl.c[i][c].im * ck.c[i][c].re;
+          }
+      }
+      re = wave_sum(re);
+      im = wave_sum(im);
+      if (lane == 0) {
+        lds[wid * 2 * NKV_MAX + 2 * l] = re;
+        lds[wid * 2 * NKV_MAX + 2 * l + 1] = im;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * k) {
+      double s = 0.0;
+      for (int w = 0; w < WG / 64; ++w) s += lds[w * 2 * NKV_MAX + threadIdx.x];
+      a.partials[(size_t)v.part * a.pw + threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// chi_k -= sum_l a_lk chi_l, then partials of |chi_k|^2 and <chi_k, r>
+__global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
+  __shared__ double lds[(WG / 64) * 3];
+  const int k = a.k;
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys]) continue;
+    const SysState& S = a.sys[v.sys];
+    Spinor<double> ck = ld64(a.chi[k], v);
+    for (int l = 0; l < k; ++l) {
+      const double2 al = S.a[l * NKV_MAX + k];
+      const cplx<double> m = {-al.x, -al.y};
+      Spinor<double> cl = ld64(a.chi[l], v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cmac(ck.c[i][c], m, cl.c[i][c]);
+    }
+    double vals[3] = {0.0, 0.0, 0.0};
+    if (v.valid) {
+      if (k > 0) st64(a.chi[k], v, ck);
+      Spinor<double> r = ld64(a.r, v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          vals[0] += ck.c[i][c].re * ck.c[i][c].re + ck.c[i][c].im * ck.c[i][c].im;
+          vals[1] += ck.c[i][c].re * r.c[i][c].re + ck.c[i][c].im * r.c[i][c].im;
+          vals[2] += ck.c[i][c].re * r.c[i][c].im - ck.c[i][c].im * r.c[i][c].re;
+        }
+    }
+    put_partial<3>(a, v, vals, lds);
+    __syncthreads();
+  }
+}
+
+// chi_k /= b_k; r -= c_k chi_k; partial |r|^2
+__global__ __launch_bounds__(WG) void k_update_r(VecLaunch a) {
+  __shared__ double lds[(WG / 64)];
+  const int k = a.k;
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys]) continue;
+    const SysState& S = a.sys[v.sys];
+    const double ib = 1.0 / S.bk[k];
+    const cplx<double> mc = {-S.ck[k].x, -S.ck[k].y};
+    double vals[1] = {0.0};
+    if (v.valid) {
+      Spinor<double> ck = ld64(a.chi[k], v);
+      Spinor<double> r = ld64(a.r, v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ck.c[i][c] = ib * ck.c[i][c];
+          cmac(r.c[i][c], mc, ck.c[i][c]);
+          vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
+        }
+      st64(a.chi[k], v, ck);
+      st64(a.r, v, r);
+    }
+    put_partial<1>(a, v, vals, lds);
+    __syncthreads();
+  }
+}
+
+// x += sum_{l < k_done} alpha_l phi_l
+__global__ __launch_bounds__(WG) void k_x_update(VecLaunch a) {
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    const SysState& S = a.sys[v.sys];
+    if (S.converged || !v.valid) continue;
+    Spinor<double> x = ld64(a.x, v);
+    for (int l = 0; l < S.k_done; ++l) {
+      const cplx<double> al = {S.alpha[l].x, S.alpha[l].y};
+      Spinor<double> p = ld64(a.phi[l], v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cmac(x.c[i][c], al, p.c[i][c]);
+    }
+    st64(a.x, v, x);
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_norm2(VecLaunch a, const double2* f) {
+  __shared__ double lds[(WG / 64)];
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    double vals[1] = {0.0};
+    if (v.valid) {
+      Spinor<double> p = ld64(f, v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vals[0] += p.c[i][c].re * p.c[i][c].re + p.c[i][c].im * p.c[i][c].im;
+    }
+    put_partial<1>(a, v, vals, lds);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_copy(VecLaunch a, double2* dst, const double2* src) {
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (!v.valid) continue;
+    st64(dst, v, ld64(src, v));
+  }
+}
+
+// ------------------------------------------------------------------ per-system reductions
+
+__global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
+  __shared__ double lds[(WG / 64) * 2 * NKV_MAX];
+  const int sys = blockIdx.x;
+  SysState& S = a.sys[sys];
+  const int nv = op == RED_MULTIDOT ? 2 * a.k : (op == RED_GS ? 3 : 1);
+  const bool global_op = (op == RED_TRUE || op == RED_BNORM || op == RED_INITR);
+  if (!global_op && (a.skip[sys] != 0)) return;
+  if ((op == RED_TRUE || op == RED_INITR) && S.converged) return;
+  if (nv == 0) return;
+  double acc[2 * NKV_MAX];
+  for (int j = 0; j < nv; ++j) acc[j] = 0.0;
+  const int p0 = sys_part[sys], nc = sys_nchunks[sys];
+  for (int c = threadIdx.x; c < nc; c += WG)
+    for (int j = 0; j < nv; ++j) acc[j] += a.partials[(size_t)(p0 + c) * a.pw + j];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = 0; j < nv; ++j) {
+    double t = wave_sum(acc[j]);
+    if (lane == 0) lds[wid * 2 * NKV_MAX + j] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double sum[2 * NKV_MAX];
+  for (int j = 0; j < nv; ++j) {
+    double t = 0.0;
+    for (int w = 0; w < WG / 64; ++w) t += lds[w * 2 * NKV_MAX + j];
+    sum[j] = t;
+  }
+  const int k = a.k;
+  switch (op) {
+    case RED_MULTIDOT:
+      for (int l = 0; l < k; ++l) S.a[l * NKV_MAX + k] = make_double2(sum[2 * l], sum[2 * l + 1]);
+      break;
+    case RED_GS: {
+      const double b = sqrt(sum[0]);
+      if (!(b > 0.0) || !isfinite(b)) {
+        S.breakdown = 1;
+        S.cycle_done = 1;
+        a.sys[sys].bk[k] = 1.0;
+        S.ck[k] = make_double2(0.0, 0.0);
+        a.skip[sys] = 1;
+        break;
+      }
+      S.bk[k] = b;
+      S.ck[k] = make_double2(sum[1] / b, sum[2] / b);
+      break;
+    }
+    case RED_RNORM:
+      S.rnorm2 = sum[0];
+      S.k_done = k + 1;
+      S.iters += 1;
+      if (!(sum[0] > S.thr2) || S.iters >= a.maxit) {
+        S.cycle_done = 1;
+        a.skip[sys] = 1;
+      }
+      break;
+    case RED_BNORM:
+      S.bnorm2 = sum[0];
+      S.rnorm2 = sum[0];
+      S.tol2 = a.tol * a.tol * sum[0];
+      S.thr2 = 0.25 * S.tol2;
+      S.cycle_done = 0;
+      S.converged = (sum[0] == 0.0);
+      S.k_done = 0;
+      S.iters = 0;
+      S.restarts = 0;
+      S.breakdown = !isfinite(sum[0]);
+      if (S.breakdown) S.converged = 1;
+      a.skip[sys] = S.converged;
+      break;
+    case RED_INITR:  // residual of a given initial guess
+      S.rnorm2 = sum[0];
+      if (!isfinite(sum[0])) S.breakdown = 1;
+      S.converged = (sum[0] <= S.tol2) || S.breakdown;
+      S.cycle_done = S.converged;
+      a.skip[sys] = S.converged;
+      break;
+    case RED_TRUE:
+      S.rnorm2 = sum[0];
+      S.restarts += 1;
+      if (!isfinite(sum[0])) S.breakdown = 1;
+      S.converged = (sum[0] <= S.tol2) || S.breakdown || S.iters >= a.maxit;
+      S.cycle_done = S.converged;
+      S.k_done = 0;
+      a.skip[sys] = S.converged;
+      break;
+  }
+}
+
+// alpha from the upper-triangular system b_k alpha_k + sum_{l>k} a_kl alpha_l = c_k
+__global__ void k_backsub(VecLaunch a, int nsys) {
+  const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sys >= nsys) return;
+  SysState& S = a.sys[sys];
+  if (S.converged) return;
+  const int n = S.k_done;
+  for (int k = n - 1; k >= 0; --k) {
+    double re = S.ck[k].x, im = S.ck[k].y;
+    for (int l = k + 1; l < n; ++l) {
+      const double2 akl = S.a[k * NKV_MAX + l], al = S.alpha[l];
+      re -= akl.x * al.x - akl.y * al.y;
+      im -= akl.x * al.y + akl.y * al.x;
+    }
+    S.alpha[k] = make_double2(re / S.bk[k], im / S.bk[k]);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <class F> static void launch_vec(F kern, const VecLaunch& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, st, a);
+}
+
+void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
+  switch (prec) {
+    case P_F64: launch_vec(k_to_sap<P_F64>, a, grid, st); break;
+    case P_F32: launch_vec(k_to_sap<P_F32>, a, grid, st); break;
+    case P_F16: launch_vec(k_to_sap<P_F16>, a, grid, st); break;
+    default: launch_vec(k_to_sap<P_BF16>, a, grid, st); break;
+  }
+}
+void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
+  switch (prec) {
+    case P_F64: launch_vec(k_from_sap<P_F64>, a, grid, st); break;
+    case P_F32: launch_vec(k_from_sap<P_F32>, a, grid, st); break;
+    case P_F16: launch_vec(k_from_sap<P_F16>, a, grid, st); break;
+    default: launch_vec(k_from_sap<P_BF16>, a, grid, st); break;
+  }
+}
+void launch_multidot(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_multidot, a, grid, st); }
+void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update, a, grid, st); }
+void launch_update_r(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_update_r, a, grid, st); }
+void launch_x_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_x_update, a, grid, st); }
+void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2, dim3(grid), dim3(WG), 0, st, a, v);
+}
+void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, st, a, dst, src);
+}
+void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(WG), 0, st, op, a, sys_part, sys_nchunks);
+}
+void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st) {
+  hipLaunchKernelGGL(k_backsub, dim3((nsys + 63) / 64), dim3(64), 0, st, a, nsys);
+}
+
+}  // namespace wc

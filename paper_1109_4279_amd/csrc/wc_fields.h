@@ -1,0 +1,316 @@
+// Field storage accessors, batch descriptors and wavefront reductions.
+#pragma once
+
+#include "wc_common.h"
+
+namespace wc {
+
+constexpr int WG = 256;  // work-group size of every site-parallel kernel
+
+// One lattice of a batch as seen by a kernel.  Spinor fields of a batch are
+// concatenated lattice after lattice, each lattice holding nrhs consecutive
+// fields in the storage layout of its precision.
+struct LatDesc {
+  Geom g;
+  const void* gauge;   // links in the storage precision of the launch
+  const float* gscale; // 16-bit link scales [V] (null otherwise)
+  const void* clov;    // clover blocks in the storage precision of the launch
+  const float* cscale; // 16-bit clover scales [V][2]
+  long long foff;      // offset of rhs 0 of this lattice in a batched spinor field, in sites*rhs units
+  int nrhs;
+  int sys0;            // batch index of this lattice's first system
+  int part0;           // offset of this lattice's first reduction partial
+  int nchunks;         // ceil(V / WG): partials per system
+  const int* tiles[2]; // tile indices of each chessboard colour (ntiles/2 each)
+};
+
+// A unit of work: WG consecutive sites (or one tile for the Schwarz kernels)
+// of one lattice, for right-hand sides [rhs0, rhs0 + nr).
+struct WorkItem {
+  int lat;
+  int chunk;
+  int rhs0;
+  int nr;
+};
+
+// Map a work index so that the items run by one XCD (work-groups are dealt to
+// the 8 XCDs round-robin) form a contiguous range, keeping neighbouring sites
+// in one L2.
+WC_D int xcd_remap(int it, int n) {
+  if (n & 7) return it;
+  return (it & 7) * (n >> 3) + (it >> 3);
+}
+
+// ------------------------------------------------------------------ spinors
+
+// A spinor field view for one right-hand side: data + (16-bit) scales.
+struct FieldRef {
+  void* d;
+  float* sc;
+  int V;
+};
+
+template <int P> struct SpinorIO;
+
+template <> struct SpinorIO<P_F64> {
+  typedef double R;
+  static WC_D Spinor<double> load(const FieldRef& f, int s) {
+    const double2* p = (const double2*)f.d + s;
+    Spinor<double> o;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      double2 v = p[(size_t)k * f.V];
+      o.c[k / 3][k % 3] = {v.x, v.y};
+    }
+    return o;
+  }
+  static WC_D void store(const FieldRef& f, int s, const Spinor<double>& o) {
+    double2* p = (double2*)f.d + s;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[(size_t)k * f.V] = make_double2(o.c[k / 3][k % 3].re, o.c[k / 3][k % 3].im);
+  }
+  static constexpr int bytes_per_site = 192;
+};
+
+template <> struct SpinorIO<P_F32> {
+  typedef float R;
+  static WC_D Spinor<float> load(const FieldRef& f, int s) {
+    const float4* p = (const float4*)f.d + s;
+    Spinor<float> o;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float4 v = p[(size_t)k * f.V];
+      int c0 = 2 * k, c1 = 2 * k + 1;
+      o.c[c0 / 3][c0 % 3] = {v.x, v.y};
+      o.c[c1 / 3][c1 % 3] = {v.z, v.w};
+    }
+    return o;
+  }
+  static WC_D void store(const FieldRef& f, int s, const Spinor<float>& o) {
+    float4* p = (float4*)f.d + s;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      int c0 = 2 * k, c1 = 2 * k + 1;
+      p[(size_t)k * f.V] = make_float4(o.c[c0 / 3][c0 % 3].re, o.c[c0 / 3][c0 % 3].im,
+                                       o.c[c1 / 3][c1 % 3].re, o.c[c1 / 3][c1 % 3].im);
+    }
+  }
+  static constexpr int bytes_per_site = 96;
+};
+
+template <int P> struct SpinorIO16 {
+  typedef float R;
+  static WC_D Spinor<float> load(const FieldRef& f, int s) {
+    const uint4* p = (const uint4*)f.d + s;
+    float sc = f.sc[s];
+    Spinor<float> o;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 v = p[(size_t)k * f.V];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int c = 4 * k + j;
+        o.c[c / 3][c % 3] = {sc * s16_to_f32<P>(uint16_t(w[j] & 0xFFFFu)), sc * s16_to_f32<P>(uint16_t(w[j] >> 16))};
+      }
+    }
+    return o;
+  }
+  static WC_D void store(const FieldRef& f, int s, const Spinor<float>& o) {
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) m = fmaxf(m, fmaxf(fabsf(o.c[i][a].re), fabsf(o.c[i][a].im)));
+    float sc = m > 0.f ? m : 1.f;
+    float inv = 1.f / sc;
+    uint4* p = (uint4*)f.d + s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int c = 4 * k + j;
+        w[j] = uint32_t(f32_to_s16<P>(o.c[c / 3][c % 3].re * inv)) |
+               (uint32_t(f32_to_s16<P>(o.c[c / 3][c % 3].im * inv)) << 16);
+      }
+      p[(size_t)k * f.V] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    f.sc[s] = sc;
+  }
+  static constexpr int bytes_per_site = 52;
+};
+template <> struct SpinorIO<P_F16> : SpinorIO16<P_F16> {};
+template <> struct SpinorIO<P_BF16> : SpinorIO16<P_BF16> {};
+
+// element size of one site of one rhs in the data array (scales separate)
+WC_HD int spinor_site_bytes(int P) { return P == P_F64 ? 192 : (P == P_F32 ? 96 : 48); }
+
+// ------------------------------------------------------------------ links
+
+template <int P> struct LinkIO;
+
+template <> struct LinkIO<P_F64> {
+  static WC_D SU3<double> load(const void* g, const float*, int V, int mu, int s) {
+    const double2* p = (const double2*)g + (size_t)mu * 9 * V + s;
+    SU3<double> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double2 v = p[(size_t)k * V];
+      u.m[k / 3][k % 3] = {v.x, v.y};
+    }
+    return u;
+  }
+};
+template <> struct LinkIO<P_F32> {
+  static WC_D SU3<float> load(const void* g, const float*, int V, int mu, int s) {
+    const float2* p = (const float2*)g + (size_t)mu * 9 * V + s;
+    SU3<float> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float2 v = p[(size_t)k * V];
+      u.m[k / 3][k % 3] = {v.x, v.y};
+    }
+    return u;
+  }
+};
+template <int P> struct LinkIO16 {
+  static WC_D SU3<float> load(const void* g, const float* sc, int V, int mu, int s) {
+    const uint4* p = (const uint4*)g + (size_t)mu * 2 * V + s;
+    const uint32_t* q = (const uint32_t*)((const uint4*)g + (size_t)8 * V) + (size_t)mu * V + s;
+    float f = sc[s];
+    uint4 a = p[0], b = p[V];
+    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, *q};
+    SU3<float> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      u.m[k / 3][k % 3] = {f * s16_to_f32<P>(uint16_t(w[k] & 0xFFFFu)), f * s16_to_f32<P>(uint16_t(w[k] >> 16))};
+    return u;
+  }
+};
+template <> struct LinkIO<P_F16> : LinkIO16<P_F16> {};
+template <> struct LinkIO<P_BF16> : LinkIO16<P_BF16> {};
+
+// bytes of the link array per site (all four directions, scales excluded)
+WC_HD int link_site_bytes(int P) { return P == P_F64 ? 576 : (P == P_F32 ? 288 : 144); }
+
+// ------------------------------------------------------------------ clover
+
+template <class R> struct Herm6 {
+  R d[6];
+  cplx<R> o[15];
+};
+
+template <int P> struct CloverIO;
+
+template <> struct CloverIO<P_F64> {
+  static WC_D Herm6<double> load(const void* c, const float*, int V, int s, int blk) {
+    const double2* p = (const double2*)c + (size_t)(18 * blk) * V + s;
+    Herm6<double> h;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double2 v = p[(size_t)k * V];
+      h.d[2 * k] = v.x;
+      h.d[2 * k + 1] = v.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 15; ++k) {
+      double2 v = p[(size_t)(3 + k) * V];
+      h.o[k] = {v.x, v.y};
+    }
+    return h;
+  }
+};
+template <> struct CloverIO<P_F32> {
+  static WC_D Herm6<float> load(const void* c, const float*, int V, int s, int blk) {
+    const float4* p = (const float4*)c + (size_t)(9 * blk) * V + s;
+    float r[36];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      float4 v = p[(size_t)k * V];
+      r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
+    }
+    Herm6<float> h;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) h.d[k] = r[k];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) h.o[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    return h;
+  }
+};
+template <int P> struct CloverIO16 {
+  // 72 halves per site in 9 uint4; reals 36*blk .. 36*blk+35 belong to block blk
+  static WC_D Herm6<float> load(const void* c, const float* sc, int V, int s, int blk) {
+    const uint4* p = (const uint4*)c + s;
+    float f = sc[2 * s + blk];
+    float r[36];
+    // block 0 uses uint4 0..4 (reals 0..39), block 1 uses uint4 4..8 (reals 32..71)
+    const int k0 = blk == 0 ? 0 : 4;
+    const int off = blk == 0 ? 0 : 4;  // reals to skip at the start of uint4 k0
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      uint4 v = p[(size_t)(k0 + k) * V];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int i0 = 8 * k + 2 * j - off, i1 = i0 + 1;
+        if (i0 >= 0 && i0 < 36) r[i0] = f * s16_to_f32<P>(uint16_t(w[j] & 0xFFFFu));
+        if (i1 >= 0 && i1 < 36) r[i1] = f * s16_to_f32<P>(uint16_t(w[j] >> 16));
+      }
+    }
+    Herm6<float> h;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) h.d[k] = r[k];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) h.o[k] = {r[6 + 2 * k], r[7 + 2 * k]};
+    return h;
+  }
+};
+template <> struct CloverIO<P_F16> : CloverIO16<P_F16> {};
+template <> struct CloverIO<P_BF16> : CloverIO16<P_BF16> {};
+
+WC_HD int clover_site_bytes(int P) { return P == P_F64 ? 576 : (P == P_F32 ? 288 : 144); }
+
+// out (6 complex) = H v for a Hermitian 6x6 stored as diagonal + upper triangle
+template <class R> WC_D void herm6_apply(const Herm6<R>& h, const cplx<R>* v, cplx<R>* out) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out[i] = h.d[i] * v[i];
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j, ++k) {
+      cmac(out[i], h.o[k], v[j]);
+      cmac_conj(out[j], h.o[k], v[i]);
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+
+template <class T> WC_D T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the work-group of up to N values per thread; result valid in every thread.
+// `lds` needs (blockDim/64) * N doubles.
+template <int N> WC_D void block_sum(double* v, double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[wid * N + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[w * N + i];
+    v[i] = s;
+  }
+}
+
+}  // namespace wc

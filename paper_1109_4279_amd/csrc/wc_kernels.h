@@ -1,0 +1,121 @@
+// Launch descriptors and host launchers of every kernel of the library.
+#pragma once
+
+#include "wc_fields.h"
+
+namespace wc {
+
+constexpr int NKV_MAX = 32;  // largest FGCR restart length
+
+// ----------------------------------------------------------------- D_w
+struct DiracLaunch {
+  const LatDesc* lats;
+  const WorkItem* items;
+  int nitems;
+  const void* in;
+  const float* in_sc;
+  void* out;
+  float* out_sc;
+  const void* y;       // if set: out = y - D in (same precision as out)
+  const float* y_sc;
+  double* partials;    // if set: |out|^2 per (system, chunk), stride pw
+  int pw;
+  const int* skip;     // if set: systems with skip != 0 are not written
+  int dagger;          // apply gamma5 D gamma5
+  int block;           // Dirichlet-block operator instead of the full one
+};
+void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
+
+// ----------------------------------------------------------------- Schwarz block MR
+struct SapLaunch {
+  const LatDesc* lats;
+  const WorkItem* items;  // chunk = index into the colour's tile list
+  int nitems;
+  int colour;
+  int nmr;
+  void* rho; float* rho_sc;
+  void* z; float* z_sc;
+  void* psi; float* psi_sc;
+  const int* skip;
+  int first;        // psi = z (else psi += z)
+  int border;       // subtract the hops out of the other colour's z before solving
+  int write_rho;
+  int write_z;
+};
+void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
+size_t sap_lds_bytes(int prec, int nr, int bvol);
+
+// ----------------------------------------------------------------- layout conversion / setup
+// canonical complex128 [rhs][V][4][3] (lexicographic) <-> internal field of one lattice
+void launch_pack_spinor(int prec, const Geom& g, int nrhs, const void* canon, void* dst, float* dst_sc,
+                        hipStream_t st);
+void launch_unpack_spinor(int prec, const Geom& g, int nrhs, const void* src, const float* src_sc, void* canon,
+                          int colour_only, hipStream_t st);
+// canonical complex128 links [4][V][3][3] -> internal links
+void launch_pack_links(int prec, const Geom& g, const void* canon, void* dst, float* dst_sc, hipStream_t st);
+// clover blocks from internal FP64 links, FP64 storage
+void launch_clover_build(const Geom& g, const void* links64, double m0, double csw, void* clov64, hipStream_t st);
+// FP64 clover -> storage precision
+void launch_clover_convert(int prec, const Geom& g, const void* clov64, void* dst, float* dst_sc, hipStream_t st);
+
+// ----------------------------------------------------------------- FGCR vector kernels
+struct SysState {
+  double bnorm2;
+  double rnorm2;       // |r|^2, recursive inside a cycle, true after a restart
+  double thr2;         // cycle stops once rnorm2 <= thr2
+  double tol2;         // solve stops once the true |r|^2 <= tol2
+  int cycle_done;
+  int converged;
+  int k_done;
+  int iters;
+  int restarts;
+  int breakdown;
+  double sap_scale;    // |r| at the current SAP input
+  double2 a[NKV_MAX * NKV_MAX];  // a[l * NKV_MAX + k] = <chi_l, chi_k>
+  double bk[NKV_MAX];
+  double2 ck[NKV_MAX];
+  double2 alpha[NKV_MAX];
+};
+
+struct VecLaunch {
+  const LatDesc* lats;
+  const WorkItem* items;   // nr = 1
+  int nitems;
+  SysState* sys;
+  int* skip;               // per system: 1 while it sits out the current cycle
+  double* partials;        // [total_chunks][pw]
+  int pw;
+  int k;                   // iteration index inside the cycle
+  int maxit;               // cap on FGCR iterations per system
+  double tol;              // relative residual target
+  // F64 batched fields
+  double2* r;
+  double2* x;
+  double2* const* chi;     // device array of NKV_MAX pointers
+  double2* const* phi;
+  // SAP-precision field for conversions
+  void* sp; float* sp_sc;
+};
+// phi_k = |r| * psi(P)      (psi from the SAP) ; eta(P) = r / |r|
+void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
+void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
+void launch_multidot(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, l < k
+void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);    // chi_k -= sum a_lk chi_l; |chi_k|^2, <chi_k, r>
+void launch_update_r(const VecLaunch& a, int grid, hipStream_t st);     // chi_k /= b_k; r -= c_k chi_k; |r|^2
+void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l
+void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials
+void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st);
+
+// per-system reductions and scalar steps (one work-group per system)
+enum ReduceOp { RED_MULTIDOT = 0, RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5 };
+void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
+                   hipStream_t st);
+void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st);
+
+// ----------------------------------------------------------------- force
+// K_mu(x) += coef * d Re<Y, D X>/dU (torch convention: G = K^dag) per link, canonical [4][V][3][3]
+void launch_link_grad(const Geom& g, const void* links64, const void* Y, const void* X, int nrhs, double csw,
+                      double coef, void* Kout, hipStream_t st);
+void launch_lie_force(const Geom& g, const void* links64, const void* K, void* F, hipStream_t st);
+
+}  // namespace wc

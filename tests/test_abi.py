@@ -1,0 +1,63 @@
+"""The C interface without a GPU: the library builds, loads, and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wc.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wc_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["wc_create_gauge", "wc_create_clover", "wc_apply_D", "wc_sap_block_mr", "wc_fgcr_solve",
+                 "wc_fgcr_solve_batch", "wc_force", "wc_link_grad", "wc_destroy", "wc_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1109_4279_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwc.so not built")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    # the Python binding declares exactly the header's entry points
+    assert sorted(_lib.exported_symbols()) == _declared()
+    lib2 = _lib.load()
+    assert lib2.wc_version() == 100
+
+
+def test_default_params_and_error_text():
+    from paper_1109_4279_amd import _lib, default_params
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwc.so not built")
+    p = default_params()
+    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit) == (16, 5, 4, 1, 10000)
+    assert abs(p.tol - 1e-10) < 1e-25
+    lib = _lib.load()
+    # argument errors are reported without touching a device
+    ctx = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    blk = (ctypes.c_int * 4)(2, 2, 2, 2)
+    assert lib.wc_create_gauge(ctypes.byref(ctx), dims, blk, None, 1, None) == -1
+    assert b"null" in lib.wc_last_error()
+    assert lib.wc_create_gauge(ctypes.byref(ctx), dims, blk, ctypes.c_void_p(16), 3, None) == -1
+    assert lib.wc_apply_D(None, None, None, 1, 0, 0, 0, None) == -1
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1109_4279_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", src, flags=re.M), f
+                assert "oracle/" not in src, f

@@ -1,0 +1,114 @@
+"""GPU parity of the clover setup and of D_w / D_Lambda against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac
+from tests.helpers import clover, gauge, lattice, maxrel, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+# (dims, block): several tiles, a ragged last work-group (V % 256 != 0), odd block extents
+CASES = [
+    ((4, 4, 4, 4), (2, 2, 2, 2)),
+    ((8, 6, 6, 6), (4, 3, 3, 3)),
+    ((8, 4, 4, 8), (4, 2, 2, 4)),
+    ((6, 4, 2, 4), (3, 2, 1, 2)),
+]
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 3e-3, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+def test_clover_blocks_match_oracle(dims, block):
+    m0, csw = -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    A = to_np(lat.clover())
+    ref = clover(dims, m0, csw)
+    assert np.abs(A[..., 0, :, :] - ref[..., :6, :6]).max() < 1e-13
+    assert np.abs(A[..., 1, :, :] - ref[..., 6:, 6:]).max() < 1e-13
+
+
+@pytest.mark.parametrize("bc_t", [1, -1])
+@pytest.mark.parametrize("dims,block", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+def test_dirac_full_matches_oracle(dims, block, prec, bc_t):
+    m0, csw = -0.1, 1.0
+    lat = lattice(dims, block, m0, csw, bc_t)
+    U, A = gauge(dims), clover(dims, m0, csw)
+    x = synth.gaussian_spinor(dims, nrhs=3, seed=7)
+    got = to_np(lat.apply_D(to_dev(x), prec=prec))
+    want = dirac.apply_D(U, A, x, bc_t)
+    assert rel(got, want) < TOL[prec]
+    if prec == "f64":
+        assert maxrel(got, want) < 1e-12
+
+
+@pytest.mark.parametrize("dims,block", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dirac_blocks_and_dagger_match_oracle(dims, block, prec):
+    m0, csw = 0.2, 1.3
+    for bc_t in (1, -1):
+        lat = lattice(dims, block, m0, csw, bc_t)
+        U, A = gauge(dims), clover(dims, m0, csw)
+        x = synth.gaussian_spinor(dims, seed=8)
+        got = to_np(lat.apply_D(to_dev(x), prec=prec, region="blocks"))
+        want = dirac.apply_D(U, A, x, bc_t, block=block)
+        assert rel(got, want) < TOL[prec]
+        got = to_np(lat.apply_D(to_dev(x), prec=prec, dagger=True))
+        want = dirac.apply_Ddag(U, A, x, bc_t)
+        assert rel(got, want) < TOL[prec]
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 5, 12])
+def test_dirac_multi_rhs_equals_single(nrhs):
+    dims, block = (8, 4, 4, 4), (2, 2, 2, 2)
+    lat = lattice(dims, block)
+    x = to_dev(synth.gaussian_spinor(dims, nrhs=nrhs, seed=9))
+    many = to_np(lat.apply_D(x))
+    for r in range(nrhs):
+        one = to_np(lat.apply_D(x[r].contiguous()))
+        assert np.array_equal(many[r], one)
+
+
+def test_dirac_full_size_16c32():
+    """The benchmark workload (16^3 x 32, 4^4 blocks, m0 = -0.1, c_sw = 1): every output
+    element against the oracle, FP64 and FP32."""
+    dims, block = (32, 16, 16, 16), (4, 4, 4, 4)
+    lat = lattice(dims, block)
+    U, A = gauge(dims), clover(dims, -0.1, 1.0)
+    x = synth.gaussian_spinor(dims, seed=synth.RHS_SEED)
+    want = dirac.apply_D(U, A, x)
+    got = to_np(lat.apply_D(to_dev(x), prec="f64"))
+    assert maxrel(got, want) < 1e-12
+    got = to_np(lat.apply_D(to_dev(x), prec="f32"))
+    assert rel(got, want) < 1e-5
+    got = to_np(lat.apply_D(to_dev(x), prec="f16"))
+    assert rel(got, want) < TOL["f16"]
+
+
+def test_dirac_gamma5_hermiticity_32c64():
+    """At 32^3 x 64 (too large to hold the oracle's clover in a test): <y, D x> = <g5 D g5 y, x>,
+    and the FP32 / 16-bit operators agree with the FP64 one within their bounds."""
+    import torch
+    dims, block = (64, 32, 32, 32), (4, 4, 4, 4)
+    lat = lattice(dims, block)
+    x = to_dev(synth.gaussian_spinor(dims, seed=1))
+    y = to_dev(synth.gaussian_spinor(dims, seed=2))
+    Dx = lat.apply_D(x)
+    Ddy = lat.apply_D(y, dagger=True)
+    lhs = torch.vdot(y.flatten(), Dx.flatten()).item()
+    rhs = torch.vdot(Ddy.flatten(), x.flatten()).item()
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+    for prec in ("f32", "f16", "bf16"):
+        d = lat.apply_D(x, prec=prec)
+        assert (torch.linalg.vector_norm(d - Dx) / torch.linalg.vector_norm(Dx)).item() < TOL[prec]
+
+
+def test_geometry_errors():
+    import paper_1109_4279_amd as wc
+    U = to_dev(gauge((4, 4, 4, 4)))
+    with pytest.raises(wc.WCError) as e:
+        wc.Lattice(U, block=(4, 4, 4, 4))  # one block per axis: no chessboard
+    assert e.value.code == -2
+    with pytest.raises(wc.WCError):
+        wc.Lattice(U, block=(3, 2, 2, 2))

@@ -1,0 +1,122 @@
+"""GPU FGCR solves: dense-LU parity on 4^4, oracle-checked true residuals, mixed precision,
+batching over right-hand sides and uneven lattices, graph replay and failure reporting."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import dense, dirac, solvers
+from tests.helpers import clover, gauge, lattice, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _true_res(dims, m0, csw, x, b, bc_t=1):
+    U, A = gauge(dims), clover(dims, m0, csw)
+    return dirac.norm(b - dirac.apply_D(U, A, x, bc_t)) / dirac.norm(b)
+
+
+@pytest.mark.parametrize("sap_prec", ["f64", "f32", "f16", "bf16"])
+def test_fgcr_4444_matches_dense_lu(sap_prec):
+    dims, block, m0, csw = (4, 4, 4, 4), (2, 2, 2, 2), 0.0, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims)
+    x, st = lat.solve(to_dev(b), nkv=8, ncy=5, nmr=4, tol=1e-10, sap_prec=sap_prec)
+    x = to_np(x)
+    assert st[0]["status"] == 0
+    assert _true_res(dims, m0, csw, x, b) <= 1e-10
+    A = clover(dims, m0, csw)
+    M = dense.assemble(gauge(dims), A)
+    xd = sla.lu_solve(sla.lu_factor(M), b.ravel()).reshape(b.shape)
+    assert rel(x, xd) < np.linalg.cond(M) * 1e-10
+    if sap_prec == "f64":
+        ref = solvers.sap_fgcr(gauge(dims), A, b, block, nmr=4, ncy=5, nkv=8, tol=1e-10)
+        assert abs(st[0]["iters"] - ref.iters) <= 1
+
+
+def test_fgcr_16c32_fp64_and_mixed():
+    dims, block, m0, csw = (32, 16, 16, 16), (4, 4, 4, 4), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims)
+    x64, st64 = lat.solve(to_dev(b), sap_prec="f64", nkv=16, ncy=5, nmr=4, tol=1e-10)
+    x32, st32 = lat.solve(to_dev(b), sap_prec="f32", nkv=16, ncy=5, nmr=4, tol=1e-10)
+    x16, st16 = lat.solve(to_dev(b), sap_prec="f16", nkv=16, ncy=5, nmr=4, tol=1e-10)
+    for x, st in ((x64, st64), (x32, st32), (x16, st16)):
+        assert st[0]["status"] == 0
+        assert _true_res(dims, m0, csw, to_np(x), b) <= 1e-10
+    assert rel(to_np(x32), to_np(x64)) < 1e-8
+
+
+def test_fgcr_antiperiodic_and_initial_guess():
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw, bc_t=-1)
+    b = synth.gaussian_spinor(dims, seed=41)
+    x, st = lat.solve(to_dev(b), tol=1e-10)
+    assert _true_res(dims, m0, csw, to_np(x), b, -1) <= 1e-10
+    # restart from the answer: converged before any iteration
+    x2, st2 = lat.solve(to_dev(b), x0=x, tol=1e-10)
+    assert st2[0]["iters"] == 0
+    assert np.array_equal(to_np(x2), to_np(x))
+
+
+def test_fgcr_multi_rhs_point_sources():
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.point_sources(dims)
+    x, st = lat.solve(to_dev(b), tol=1e-10, sap_prec="f32")
+    x = to_np(x)
+    for r in range(12):
+        assert st[r]["status"] == 0
+        assert _true_res(dims, m0, csw, x[r], b[r]) <= 1e-10
+    one, _ = lat.solve(to_dev(b[5]), tol=1e-10, sap_prec="f32")
+    assert rel(x[5], to_np(one)) < 1e-8
+
+
+def test_fgcr_uneven_batch():
+    import paper_1109_4279_amd as wc
+    m0, csw = -0.1, 1.0
+    specs = [((16, 8, 8, 8), (4, 4, 4, 4)), ((24, 12, 12, 12), (4, 3, 3, 3)), ((8, 4, 4, 4), (2, 2, 2, 2))]
+    lats, bs = [], []
+    for i, (dims, block) in enumerate(specs):
+        lats.append(lattice(dims, block, m0, csw, seed=synth.GAUGE_SEED + i))
+        bs.append(synth.gaussian_spinor(dims, nrhs=4, seed=synth.RHS_SEED + i))
+    xs, st = wc.solve_batch(lats, [to_dev(b) for b in bs], tol=1e-10, sap_prec="f32")
+    k = 0
+    for i, (dims, block) in enumerate(specs):
+        U = synth.gauge_field(dims, seed=synth.GAUGE_SEED + i)
+        A = dirac.clover_matrix(U, m0, csw)
+        x = to_np(xs[i])
+        for r in range(4):
+            assert st[k]["status"] == 0
+            res = dirac.norm(bs[i][r] - dirac.apply_D(U, A, x[r])) / dirac.norm(bs[i][r])
+            assert res <= 1e-10
+            k += 1
+
+
+def test_graph_replay_equals_eager():
+    dims, block = (8, 4, 4, 4), (2, 2, 2, 2)
+    lat = lattice(dims, block)
+    b = to_dev(synth.gaussian_spinor(dims, nrhs=2, seed=43))
+    xg, sg = lat.solve(b, tol=1e-10, use_graph=1)
+    xe, se = lat.solve(b, tol=1e-10, use_graph=0)
+    xg2, _ = lat.solve(b, tol=1e-10, use_graph=1)
+    assert np.array_equal(to_np(xg), to_np(xe))
+    assert np.array_equal(to_np(xg), to_np(xg2))
+    assert [s["iters"] for s in sg] == [s["iters"] for s in se]
+
+
+def test_not_converged_and_breakdown_reported():
+    import paper_1109_4279_amd as wc
+    dims, block = (8, 4, 4, 4), (2, 2, 2, 2)
+    lat = lattice(dims, block)
+    b = to_dev(synth.gaussian_spinor(dims, seed=44))
+    x, st = lat.solve(b, tol=1e-10, maxit=2, nkv=2, check=False)
+    assert st[0]["status"] == -5
+    assert st[0]["iters"] == 2
+    with pytest.raises(wc.WCError) as e:
+        lat.solve(b, tol=1e-10, maxit=2, nkv=2)
+    assert e.value.code == -5
+    bn = b.clone()
+    bn[0, 0, 0, 0, 0, 0] = float("nan")
+    x, st = lat.solve(bn, tol=1e-10, check=False)
+    assert st[0]["status"] in (-6, -5)
