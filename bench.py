@@ -1,0 +1,200 @@
+"""Benchmark of the Wilson-clover SAP-FGCR hot path on one MI355X.
+
+One step = one complete mixed-precision solve D x = b to a true FP64 residual of 1e-10
+(FP32 Schwarz preconditioner on FP32 storage, FP64 outer FGCR) on the 16^3 x 32 lattice
+(gauge recipe eps = 0.3, m0 = -0.1, c_sw = 1, 4^4 Schwarz blocks, 4 MR steps, 5 SAP
+cycles, restart 16, one Gaussian source), inputs resident on the device.
+
+`value` is the sustained solver throughput in Gflop/s (nominal flops of every kernel of
+the solve divided by the step time).  Beside it: the FP64-method solve time on the same
+system, D_w GB/s and Gflop/s per storage precision against the 8 TB/s HBM roofline, the
+roofline record of the dominant kernel (the Schwarz block solver), and the FP64 oracle
+timed on the host for a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DIMS = (32, 16, 16, 16)
+BLOCK = (4, 4, 4, 4)
+M0, CSW = -0.1, 1.0
+NKV, NCY, NMR, TOL = 16, 5, 4, 1e-10
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+# algorithmic bytes per site of one D_w application: spinor in + out, 4 links, 2 clover blocks
+DW_BYTES = {"f64": 192 + 192 + 576 + 576, "f32": 96 + 96 + 288 + 288, "f16": 52 + 52 + 148 + 152,
+            "bf16": 52 + 52 + 148 + 152}
+DW_FLOPS = 1320 + 504
+# Schwarz half-sweep, per solved site (FP32 storage): links + clover of the block, residual in and
+# out, block solution out, psi in and out, and the neighbouring blocks' solution read once
+SAP_BYTES_F32 = 288 + 288 + 96 * 2 + 96 + 96 * 2 + 96
+MR_VEC_FLOPS = 336          # per site and MR step: <q,rho>, <q,q>, z += a rho, rho -= a q
+BORDER_FLOPS_4444 = 2 * 168  # 2 cross-block hops per site on 4^4 blocks (project + SU(3) + add)
+
+
+def sap_flops_per_site(ncy, nmr):
+    """Nominal flops of one SAP application per lattice site (R22: 1824 per D_Lambda site)."""
+    per_half = nmr * (DW_FLOPS + MR_VEC_FLOPS) + 24
+    return ncy * per_half + (ncy - 0.5) * BORDER_FLOPS_4444
+
+
+def solve_flops(V, iters, restarts, nkv, ncy, nmr):
+    """Nominal flops of a restarted SAP-FGCR solve with `iters` iterations over `restarts` cycles."""
+    f = 0.0
+    left = iters
+    for _ in range(max(restarts, 1)):
+        kd = min(nkv, left)
+        left -= kd
+        for k in range(kd):
+            f += sap_flops_per_site(ncy, nmr) + 48       # preconditioner + scaling in/out
+            f += DW_FLOPS                                  # chi = D phi (FP64)
+            f += 2 * 96 * k + 144 + 168                     # CGS dots + update, norms, r update
+        f += 96 * kd + DW_FLOPS + 72                        # x update, true residual
+    return f * V
+
+
+def cpu_baseline(U, b):
+    """The FP64 oracle on a bounded sample of the same workload: one FGCR iteration
+    (one SAP application with 4 MR steps x 5 cycles, chi = D phi, Gram-Schmidt) on the
+    16^3 x 32 system, single thread, reported in the same Gflop/s unit."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dirac, solvers
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        A = dirac.clover_matrix(U, M0, CSW)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res = solvers.fgcr(lambda v: dirac.apply_D(U, A, v),
+                           lambda v: solvers.sap(U, A, v, BLOCK, NMR, NCY),
+                           b, tol=1e-300, nkv=NKV, maxit=1)
+        t = time.perf_counter() - t0
+    V = int(np.prod(DIMS))
+    fl = solve_flops(V, 1, 1, NKV, NCY, NMR)
+    return {"value": fl / t / 1e9, "unit": "Gflop/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FGCR iteration (SAP {NCY} cycles x {NMR} MR + FP64 D + GS + true residual) of the "
+                      f"16^3x32 workload, numpy FP64, 1 thread; {t:.1f} s (clover setup {t_setup:.1f} s not counted)",
+            "seconds": t, "iters_done": res.iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--profile", action="store_true", help="short run for profilers: no CPU leg, few kernels")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding design is "
+              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1109_4279_amd as wc
+    import synth
+
+    dev = torch.device("cuda:0")
+    U_np = synth.gauge_field(DIMS)
+    b_np = synth.gaussian_spinor(DIMS)
+    U = torch.from_numpy(U_np).to(dev)
+    b = torch.from_numpy(b_np).to(dev)
+    lat = wc.Lattice(U, block=BLOCK, m0=M0, csw=CSW)
+    V = lat.volume
+    mixed = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f32", use_graph=1)
+    plain = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f64", use_graph=1)
+
+    for _ in range(args.warmup):
+        lat.solve(b, mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        x, st = lat.solve(b, mixed)
+        stats.append(st[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    st = stats[-1]
+    # the answer, checked with the library's own FP64 operator
+    r = b - lat.apply_D(x)
+    rel_res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+    flops = solve_flops(V, st["iters"], st["restarts"], NKV, NCY, NMR)
+    value = flops / (ms_per_step * 1e-3) / 1e9
+
+    # the plain FP64 method on the same system
+    lat.solve(b, plain)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    x64, st64 = lat.solve(b, plain)
+    torch.cuda.synchronize()
+    tts_fp64 = (time.perf_counter() - tp0) * 1e3
+    rel_err = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
+
+    # D_w per storage precision (HIP events inside the library, same stream)
+    dw = {}
+    for prec in ("f64", "f32", "f16", "bf16"):
+        ms = lat.bench_dirac(prec=prec, nrhs=1, iters=20 if args.profile else 100)
+        gbs = DW_BYTES[prec] * V / (ms * 1e-3) / 1e9
+        dw[prec] = {"ms": ms, "GB/s": gbs, "Gflop/s": DW_FLOPS * V / (ms * 1e-3) / 1e9,
+                    "frac_hbm": gbs / HBM_PEAK_GBS}
+    # dominant kernel of the step: the FP32 Schwarz half-sweep
+    ms_sap = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, iters=20 if args.profile else 100)
+    sites = V // 2
+    sap_bytes = SAP_BYTES_F32 * sites
+    sap_flops = (NMR * (DW_FLOPS + MR_VEC_FLOPS) + BORDER_FLOPS_4444 + 24) * sites
+    ach = sap_bytes / (ms_sap * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "kernel": "k_sap_mr<F32,1> (one colour, 4^4 blocks)",
+                "launch_ms": ms_sap, "alg_bytes_per_launch": sap_bytes,
+                "tflops": sap_flops / (ms_sap * 1e-3) / 1e12,
+                "frac_fp32_peak": sap_flops / (ms_sap * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+
+    cpu = None
+    if not args.no_cpu and not args.profile:
+        cpu = cpu_baseline(U_np, b_np)
+
+    out = {
+        "metric": "D_w GB/s & Gflop/s vs HBM roofline; FGCR time-to-1e-10 (mixed vs FP64)",
+        "value": value,
+        "unit": "Gflop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "SAP-FGCR solve to 1e-10, 16^3x32, eps=0.3 gauge, m0=-0.1, c_sw=1, "
+                               "blocks 4^4, nmr=4, ncy=5, nkv=16, 1 Gaussian rhs, FP32 SAP / FP64 outer",
+                   "lattice": list(DIMS), "block": list(BLOCK), "parallelism": "single GPU"},
+        "tts_mixed_ms": ms_per_step,
+        "tts_fp64_ms": tts_fp64,
+        "speedup_mixed_vs_fp64": tts_fp64 / ms_per_step,
+        "iters_mixed": st["iters"], "restarts_mixed": st["restarts"],
+        "iters_fp64": st64[0]["iters"],
+        "true_rel_residual": rel_res, "rel_err_mixed_vs_fp64": rel_err,
+        "dirac": dw,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
