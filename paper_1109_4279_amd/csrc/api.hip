@@ -3,6 +3,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -189,6 +190,7 @@ struct Batch {
   long long sites_rhs = 0;
   int total_chunks = 0;
   int max_bvol = 0;
+  int uniform_bvol = 0;  // block volume shared by all lattices, 0 if they differ
   std::vector<LatDesc> h_lats[4];
   DevBuf d_lats[4];
   bool have_lats[4] = {false, false, false, false};
@@ -232,6 +234,9 @@ struct Batch {
       total_chunks += nrhs[i] * nch;
       max_bvol = std::max(max_bvol, g.bvol);
     }
+    uniform_bvol = lat[0]->g.bvol;
+    for (auto* c : lat)
+      if (c->g.bvol != uniform_bvol) uniform_bvol = 0;
     sys_part.ensure(sizeof(int) * nsys);
     sys_nchunks.ensure(sizeof(int) * nsys);
     HIPCK(hipMemcpy(sys_part.p, h_part.data(), sizeof(int) * nsys, hipMemcpyHostToDevice));
@@ -296,8 +301,8 @@ struct Batch {
     std::vector<WorkItem> v;
     for (size_t i = 0; i < lat.size(); ++i) {
       const int nt = lat[i]->g.ntiles / 2;
-      for (int r0 = 0; r0 < nrhs[i]; r0 += nr)
-        for (int t = 0; t < nt; ++t) v.push_back(WorkItem{(int)i, t, r0, std::min(nr, nrhs[i] - r0)});
+      for (int t = 0; t < nt; ++t)
+        for (int r0 = 0; r0 < nrhs[i]; r0 += nr) v.push_back(WorkItem{(int)i, t, r0, std::min(nr, nrhs[i] - r0)});
     }
     ItemList& L = sap_items[colour][nr];
     L.d.ensure(sizeof(WorkItem) * v.size());
@@ -323,7 +328,7 @@ static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
 
 static int default_nr(int nrhs, int prec, bool sap) {
   if (nrhs <= 1) return 1;
-  if (sap) return prec == P_F64 ? 1 : 2;
+  if (sap) return 1;
   return nrhs >= 4 ? 4 : nrhs;
 }
 
@@ -360,10 +365,34 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
 }
 
+// Register caching of the block operator pays when the launch has about one work-group
+// per CU (then nothing else could hide the reload latency); WC_SAP_CACHE=0/1 forces it.
+static int sap_cache_mode(int nitems) {
+  static int forced = -2;
+  if (forced == -2) {
+    const char* e = getenv("WC_SAP_CACHE");
+    forced = e ? atoi(e) : -1;
+  }
+  if (forced >= 0) return forced;
+  return nitems <= 2 * device_cus() ? 1 : 0;
+}
+
+// The one-lane-per-site block solver is the default; WC_SAP_KERNEL=3 selects the
+// colour-split kernel for FP32 arithmetic with one rhs per work-group.
+static bool sap_colour_split(int prec, int nr) {
+  static int forced = -2;
+  if (forced == -2) {
+    const char* e = getenv("WC_SAP_KERNEL");
+    forced = e ? atoi(e) : -1;
+  }
+  return forced == 3 && prec != P_F64 && nr == 1;
+}
+
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
                               const int* skip, int first, int border, int wrho, int wz, hipStream_t st) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
   require(sap_lds_bytes(prec, nr, B.sap_threads()) <= 65536, WC_ERR_GEOMETRY, "block too large for LDS");
+  const bool split = sap_colour_split(prec, nr);
   const LatDesc* L = B.lats(prec, st);
   const ItemList& it = B.items_sap(colour, nr);
   SapLaunch a;
@@ -383,7 +412,13 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.border = border;
   a.write_rho = wrho;
   a.write_z = wz;
-  launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), B.sap_threads(), st);
+  a.cache = sap_cache_mode(it.n);
+  a.uniform_bvol = B.uniform_bvol;
+  if (split)
+    launch_sap_mr3(prec, a, persistent_grid(it.n, 2), ((3 * B.max_bvol + 63) / 64) * 64, B.max_bvol,
+                   B.uniform_bvol, st);
+  else
+    launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), B.sap_threads(), st);
 }
 
 // ncy Schwarz cycles on rho (source), accumulating psi
@@ -921,19 +956,34 @@ int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_
   return rc != WC_OK ? rc : rc_solve;
 }
 
-static double time_launches(hipStream_t st, int iters, const std::function<void()>& f) {
+// Mean time per launch of f: `iters` launches captured into one hipGraph (so host-side
+// launch overhead does not enter), replayed between two events on `st`.
+static double time_launches(wc_ctx* c, hipStream_t st, int iters, const std::function<void(hipStream_t)>& f) {
+  f(st);  // warm-up (twice: alternating launches such as the two SAP colours) creates
+  f(st);  // every buffer and work list the captured launches touch
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(st));
+  if (!c->cap) HIPCK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  HIPCK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < iters; ++i) f(c->cap);
+  HIPCK(hipStreamEndCapture(c->cap, &graph));
+  HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  HIPCK(hipGraphDestroy(graph));
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
-  f();  // warm-up
+  HIPCK(hipGraphLaunch(exec, st));
   HIPCK(hipEventRecord(e0, st));
-  for (int i = 0; i < iters; ++i) f();
+  HIPCK(hipGraphLaunch(exec, st));
   HIPCK(hipEventRecord(e1, st));
   HIPCK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(exec);
   return double(ms) / iters;
 }
 
@@ -949,8 +999,8 @@ int wc_bench_dirac(wc_ctx* c, int prec, int nrhs, int region, int iters, double*
     HIPCK(hipMemsetAsync(B.ain[prec].data(), 0, spinor_bytes(prec, B.sites_rhs), st));
     if (B.ain[prec].scale()) HIPCK(hipMemsetAsync(B.ain[prec].scale(), 0, sizeof(float) * B.sites_rhs, st));
     const int nr = pick_nr(c, nrhs, prec, false, 0);
-    *ms = time_launches(st, iters, [&] {
-      run_dirac(B, prec, nr, B.ain[prec], B.aout[prec], nullptr, nullptr, nullptr, 0, region == WC_BLOCKS, st);
+    *ms = time_launches(c, st, iters, [&](hipStream_t s) {
+      run_dirac(B, prec, nr, B.ain[prec], B.aout[prec], nullptr, nullptr, nullptr, 0, region == WC_BLOCKS, s);
     });
     HIPCK(hipGetLastError());
   });
@@ -974,8 +1024,8 @@ int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int iters, double* ms, 
     }
     const int nr = pick_nr(c, nrhs, prec, true, 0);
     int colour = 0;
-    *ms = time_launches(st, iters, [&] {
-      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, st);
+    *ms = time_launches(c, st, iters, [&](hipStream_t s) {
+      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, s);
       colour ^= 1;
     });
     HIPCK(hipGetLastError());

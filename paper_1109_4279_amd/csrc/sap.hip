@@ -15,7 +15,9 @@ namespace wc {
 
 constexpr int SAP_MAX_WAVES = 4;  // blocks of at most 256 sites
 
-template <int P, int NR>
+// BV > 0 fixes the block volume at compile time so that every LDS offset of the residual
+// exchange is an immediate (no per-neighbour address registers); BV = 0 reads it at run time.
+template <int P, int NR, bool CACHE, int BV>
 __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
   typedef typename Real<P>::T R;
   extern __shared__ double smem_d[];
@@ -90,7 +92,32 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
       border(std::integral_constant<int, 3>());
     }
 
-    const int bvol = g.bvol;
+    const int bvol = BV > 0 ? BV : g.bvol;
+    // Operator data of this site for the in-block hops and the clover term.  With CACHE it
+    // is loaded once per half-sweep and kept in registers across the MR steps (this needs
+    // the whole register file of a SIMD, one wavefront each); otherwise it is reloaded
+    // from the caches each step and two work-groups can share a CU.
+    SU3<R> Uf[CACHE ? 4 : 1], Ub[CACHE ? 4 : 1];
+    Herm6<R> Cl[CACHE ? 2 : 1];
+    int nfw[4], nbw[4], phf[4], phb[4];
+    bool inf[4], inb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      bool same;
+      nfw[mu] = neighbour(g, s, tile, tc, lc, mu, +1, &phf[mu], &same);
+      inf[mu] = same && active;
+      nbw[mu] = neighbour(g, s, tile, tc, lc, mu, -1, &phb[mu], &same);
+      inb[mu] = same && active;
+    }
+    if (CACHE) {
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) {
+        Uf[CACHE ? mu : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, mu, s);
+        Ub[CACHE ? mu : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, mu, inb[mu] ? nbw[mu] : s);
+      }
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) Cl[CACHE ? blk : 0] = CloverIO<P>::load(L.clov, L.cscale, g.V, s, blk);
+    }
     for (int it = 0; it < a.nmr; ++it) {
       if (active) {
 #pragma unroll
@@ -105,30 +132,26 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
       if (active) {
         auto hop = [&](auto MUc) {
           constexpr int MU = decltype(MUc)::value;
-          int ph;
-          bool same;
-          int nf = neighbour(g, s, tile, tc, lc, MU, +1, &ph, &same);
-          if (same) {
-            const int ln = nf - tile * bvol;
-            SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, s);
+          if (inf[MU]) {
+            const int ln = nfw[MU] - tile * bvol;
+            SU3<R> u = CACHE ? Uf[CACHE ? MU : 0] : LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, s);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               Spinor<R> p;
 #pragma unroll
               for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * bvol + ln];
-              accum_recon<R, MU, -1>(q[r], mul_U(u, project<R, MU, -1>(p)), R(ph));
+              accum_recon<R, MU, -1>(q[r], mul_U(u, project<R, MU, -1>(p)), R(phf[MU]));
             }
           }
-          int nb = neighbour(g, s, tile, tc, lc, MU, -1, &ph, &same);
-          if (same) {
-            const int ln = nb - tile * bvol;
-            SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, nb);
+          if (inb[MU]) {
+            const int ln = nbw[MU] - tile * bvol;
+            SU3<R> u = CACHE ? Ub[CACHE ? MU : 0] : LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, nbw[MU]);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               Spinor<R> p;
 #pragma unroll
               for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * bvol + ln];
-              accum_recon<R, MU, +1>(q[r], mul_Udag(u, project<R, MU, +1>(p)), R(ph));
+              accum_recon<R, MU, +1>(q[r], mul_Udag(u, project<R, MU, +1>(p)), R(phb[MU]));
             }
           }
         };
@@ -138,7 +161,7 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
         hop(std::integral_constant<int, 3>());
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
-          Herm6<R> hc = CloverIO<P>::load(L.clov, L.cscale, g.V, s, blk);
+          Herm6<R> hc = CACHE ? Cl[CACHE ? blk : 0] : CloverIO<P>::load(L.clov, L.cscale, g.V, s, blk);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             cplx<R> v[6], o[6];
@@ -215,12 +238,31 @@ size_t sap_lds_bytes(int prec, int nr, int bvol) {
   return sizeof(double) * SAP_MAX_WAVES * 3 * nr + cb * 12 * (size_t)nr * bvol;
 }
 
+template <int P, bool C, int BV>
+static void launch_pcb(const SapLaunch& a, int nr, int grid, int threads, size_t lds, hipStream_t st) {
+  if (nr <= 1)
+    hipLaunchKernelGGL((k_sap_mr<P, 1, C, BV>), dim3(grid), dim3(threads), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_sap_mr<P, 2, C, BV>), dim3(grid), dim3(threads), lds, st, a);
+}
+
+template <int P, bool C>
+static void launch_pc(const SapLaunch& a, int nr, int grid, int threads, size_t lds, hipStream_t st) {
+  if (a.uniform_bvol == 256)
+    launch_pcb<P, C, 256>(a, nr, grid, threads, lds, st);
+  else
+    launch_pcb<P, C, 0>(a, nr, grid, threads, lds, st);
+}
+
 template <int P>
 static void launch_p(const SapLaunch& a, int nr, int grid, int threads, size_t lds, hipStream_t st) {
-  switch (nr) {
-    case 1: hipLaunchKernelGGL((k_sap_mr<P, 1>), dim3(grid), dim3(threads), lds, st, a); break;
-    default: hipLaunchKernelGGL((k_sap_mr<P, 2>), dim3(grid), dim3(threads), lds, st, a); break;
+  if constexpr (P != P_F64) {
+    if (a.cache) {
+      launch_pc<P, true>(a, nr, grid, threads, lds, st);
+      return;
+    }
   }
+  launch_pc<P, false>(a, nr, grid, threads, lds, st);
 }
 
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int threads, hipStream_t st) {

@@ -41,9 +41,15 @@ struct SapLaunch {
   int border;       // subtract the hops out of the other colour's z before solving
   int write_rho;
   int write_z;
+  int cache;        // keep links and clover in registers across the MR steps (FP32 math only)
+  int uniform_bvol; // block volume shared by every lattice of the launch (0 if they differ)
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
+// one lane per (site, colour); FP32 arithmetic precisions, one rhs per work-group
+void launch_sap_mr3(int prec, const SapLaunch& a, int grid, int threads, int max_bvol, int uniform_bvol,
+                    hipStream_t st);
+size_t sap3_lds_bytes(int bvol);
 
 // ----------------------------------------------------------------- layout conversion / setup
 // canonical complex128 [rhs][V][4][3] (lexicographic) <-> internal field of one lattice
