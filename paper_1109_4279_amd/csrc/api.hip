@@ -198,7 +198,7 @@ struct Batch {
   std::map<int, ItemList> sap_items[2];     // by RHS tile
   DevBuf sys_part, sys_nchunks;
   DevBuf partials;
-  int pw = 2 * NKV_MAX;
+  int pw = 4 * NKV_MAX;
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
   DevBuf d_chi, d_phi;
@@ -329,6 +329,8 @@ static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
 static int default_nr(int nrhs, int prec, bool sap) {
   if (nrhs <= 1) return 1;
   if (sap) return 1;
+  // FP64 with four rhs per lane spills; two fit in the register file
+  if (prec == P_F64) return 2;
   return nrhs >= 4 ? 4 : nrhs;
 }
 
@@ -530,13 +532,10 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
     launch_from_sap(s.sap_prec, vs, gv, st);
     // chi_k = D phi_k in FP64
     run_dirac(B, P_F64, s.nr_d, B.phi[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
-    if (k > 0) {
-      launch_multidot(va, gv, st);
-      launch_reduce(RED_MULTIDOT, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    }
-    launch_gs_update(va, gv, st);
+    // classical Gram-Schmidt in two passes: all inner products, then the update of chi_k and r
+    launch_gs_dots(va, gv, st);
     launch_reduce(RED_GS, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    launch_update_r(va, gv, st);
+    launch_gs_update(va, gv, st);
     launch_reduce(RED_RNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   }
   // x += sum alpha phi; r = b - D x in FP64

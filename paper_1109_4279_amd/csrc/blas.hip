@@ -88,46 +88,74 @@ __global__ __launch_bounds__(WG) void k_from_sap(VecLaunch a) {
 
 // ------------------------------------------------------------------ Gram-Schmidt
 
-__global__ __launch_bounds__(WG) void k_multidot(VecLaunch a) {
-  __shared__ double lds[(WG / 64) * 2 * NKV_MAX];
+// One pass over chi_k, r and chi_0..chi_{k-1}: partial sums of
+//   a_l = <chi_l, chi_k>, e_l = <chi_l, r> (l < k), |chi_k|^2 and <chi_k, r>.
+// With them the reduction gets the classical Gram-Schmidt coefficients a_lk, the norm
+// b_k of chi_k - sum a_lk chi_l (|chi_k|^2 - sum |a_lk|^2, the chi_l being orthonormal)
+// and c_k = <chi_k - sum a_lk chi_l, r> / b_k without a second pass.
+// Partial layout per chunk: [2k a][2k e][|chi_k|^2][2 <chi_k, r>].
+__global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
+  __shared__ double lds[(WG / 64) * (4 * NKV_MAX + 4)];
   const int k = a.k;
+  const int nv = 4 * k + 3;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys]) continue;
-    Spinor<double> ck = ld64(a.chi[k], v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Spinor<double> ck = ld64(a.chi[k], v);
+    Spinor<double> r = ld64(a.r, v);
+    if (!v.valid) {
+      zero(ck);
+      zero(r);
+    }
+    auto put = [&](int j, double x) {
+      x = wave_sum(x);
+      if (lane == 0) lds[wid * (4 * NKV_MAX + 4) + j] = x;
+    };
     for (int l = 0; l < k; ++l) {
       Spinor<double> cl = ld64(a.chi[l], v);
-      double re = 0.0, im = 0.0;
-      if (v.valid) {
+      double are = 0.0, aim = 0.0, ere = 0.0, eim = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            re += cl.c[i][c].re * ck.c[i][c].re + cl.c[i][c].im * ck.c[i][c].im;
-            im += cl.c[i][c].re * ck.c[i][c].im - cl.c[i][c].im * ck.c[i][c].re;
-          }
-      }
-      re = wave_sum(re);
-      im = wave_sum(im);
-      if (lane == 0) {
-        lds[wid * 2 * NKV_MAX + 2 * l] = re;
-        lds[wid * 2 * NKV_MAX + 2 * l + 1] = im;
-      }
+        for (int c = 0; c < 3; ++c) {
+          const cplx<double> x = cl.c[i][c];
+          are += x.re * ck.c[i][c].re + x.im * ck.c[i][c].im;
+          aim += x.re * ck.c[i][c].im - x.im * ck.c[i][c].re;
+          ere += x.re * r.c[i][c].re + x.im * r.c[i][c].im;
+          eim += x.re * r.c[i][c].im - x.im * r.c[i][c].re;
+        }
+      put(2 * l, are);
+      put(2 * l + 1, aim);
+      put(2 * k + 2 * l, ere);
+      put(2 * k + 2 * l + 1, eim);
     }
+    double n2 = 0.0, cre = 0.0, cim = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cplx<double> x = ck.c[i][c];
+        n2 += x.re * x.re + x.im * x.im;
+        cre += x.re * r.c[i][c].re + x.im * r.c[i][c].im;
+        cim += x.re * r.c[i][c].im - x.im * r.c[i][c].re;
+      }
+    put(4 * k, n2);
+    put(4 * k + 1, cre);
+    put(4 * k + 2, cim);
     __syncthreads();
-    if (threadIdx.x < 2 * k) {
-      double s = 0.0;
-      for (int w = 0; w < WG / 64; ++w) s += lds[w * 2 * NKV_MAX + threadIdx.x];
-      a.partials[(size_t)v.part * a.pw + threadIdx.x] = s;
+    for (int j = threadIdx.x; j < nv; j += WG) {
+      double t = 0.0;
+      for (int w = 0; w < WG / 64; ++w) t += lds[w * (4 * NKV_MAX + 4) + j];
+      a.partials[(size_t)v.part * a.pw + j] = t;
     }
     __syncthreads();
   }
 }
 
-// chi_k -= sum_l a_lk chi_l, then partials of |chi_k|^2 and <chi_k, r>
+// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2
 __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
-  __shared__ double lds[(WG / 64) * 3];
+  __shared__ double lds[(WG / 64)];
   const int k = a.k;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
@@ -143,37 +171,10 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) cmac(ck.c[i][c], m, cl.c[i][c]);
     }
-    double vals[3] = {0.0, 0.0, 0.0};
-    if (v.valid) {
-      if (k > 0) st64(a.chi[k], v, ck);
-      Spinor<double> r = ld64(a.r, v);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          vals[0] += ck.c[i][c].re * ck.c[i][c].re + ck.c[i][c].im * ck.c[i][c].im;
-          vals[1] += ck.c[i][c].re * r.c[i][c].re + ck.c[i][c].im * r.c[i][c].im;
-          vals[2] += ck.c[i][c].re * r.c[i][c].im - ck.c[i][c].im * r.c[i][c].re;
-        }
-    }
-    put_partial<3>(a, v, vals, lds);
-    __syncthreads();
-  }
-}
-
-// chi_k /= b_k; r -= c_k chi_k; partial |r|^2
-__global__ __launch_bounds__(WG) void k_update_r(VecLaunch a) {
-  __shared__ double lds[(WG / 64)];
-  const int k = a.k;
-  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
-    VecSite v = vec_site(a, it0);
-    if (a.skip[v.sys]) continue;
-    const SysState& S = a.sys[v.sys];
     const double ib = 1.0 / S.bk[k];
     const cplx<double> mc = {-S.ck[k].x, -S.ck[k].y};
     double vals[1] = {0.0};
     if (v.valid) {
-      Spinor<double> ck = ld64(a.chi[k], v);
       Spinor<double> r = ld64(a.r, v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -238,15 +239,15 @@ __global__ __launch_bounds__(WG) void k_copy(VecLaunch a, double2* dst, const do
 // ------------------------------------------------------------------ per-system reductions
 
 __global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
-  __shared__ double lds[(WG / 64) * 2 * NKV_MAX];
+  __shared__ double lds[(WG / 64) * 4 * NKV_MAX];
   const int sys = blockIdx.x;
   SysState& S = a.sys[sys];
-  const int nv = op == RED_MULTIDOT ? 2 * a.k : (op == RED_GS ? 3 : 1);
+  const int nv = op == RED_GS ? 4 * a.k + 3 : 1;
   const bool global_op = (op == RED_TRUE || op == RED_BNORM || op == RED_INITR);
   if (!global_op && (a.skip[sys] != 0)) return;
   if ((op == RED_TRUE || op == RED_INITR) && S.converged) return;
   if (nv == 0) return;
-  double acc[2 * NKV_MAX];
+  double acc[4 * NKV_MAX];
   for (int j = 0; j < nv; ++j) acc[j] = 0.0;
   const int p0 = sys_part[sys], nc = sys_nchunks[sys];
   for (int c = threadIdx.x; c < nc; c += WG)
@@ -254,33 +255,40 @@ __global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* s
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int j = 0; j < nv; ++j) {
     double t = wave_sum(acc[j]);
-    if (lane == 0) lds[wid * 2 * NKV_MAX + j] = t;
+    if (lane == 0) lds[wid * 4 * NKV_MAX + j] = t;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double sum[2 * NKV_MAX];
+  double sum[4 * NKV_MAX];
   for (int j = 0; j < nv; ++j) {
     double t = 0.0;
-    for (int w = 0; w < WG / 64; ++w) t += lds[w * 2 * NKV_MAX + j];
+    for (int w = 0; w < WG / 64; ++w) t += lds[w * 4 * NKV_MAX + j];
     sum[j] = t;
   }
   const int k = a.k;
   switch (op) {
-    case RED_MULTIDOT:
-      for (int l = 0; l < k; ++l) S.a[l * NKV_MAX + k] = make_double2(sum[2 * l], sum[2 * l + 1]);
-      break;
     case RED_GS: {
-      const double b = sqrt(sum[0]);
-      if (!(b > 0.0) || !isfinite(b)) {
+      // a_lk, b_k^2 = |chi_k|^2 - sum |a_lk|^2, c_k = (<chi_k, r> - sum conj(a_lk) <chi_l, r>) / b_k
+      double b2 = sum[4 * k], cre = sum[4 * k + 1], cim = sum[4 * k + 2];
+      for (int l = 0; l < k; ++l) {
+        const double are = sum[2 * l], aim = sum[2 * l + 1];
+        const double ere = sum[2 * k + 2 * l], eim = sum[2 * k + 2 * l + 1];
+        S.a[l * NKV_MAX + k] = make_double2(are, aim);
+        b2 -= are * are + aim * aim;
+        cre -= are * ere + aim * eim;
+        cim -= are * eim - aim * ere;
+      }
+      const double b = sqrt(b2);
+      if (!(b2 > 1e-24 * sum[4 * k]) || !isfinite(b)) {
         S.breakdown = 1;
         S.cycle_done = 1;
-        a.sys[sys].bk[k] = 1.0;
+        S.bk[k] = 1.0;
         S.ck[k] = make_double2(0.0, 0.0);
         a.skip[sys] = 1;
         break;
       }
       S.bk[k] = b;
-      S.ck[k] = make_double2(sum[1] / b, sum[2] / b);
+      S.ck[k] = make_double2(cre / b, cim / b);
       break;
     }
     case RED_RNORM:
@@ -365,9 +373,8 @@ void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
     default: launch_vec(k_from_sap<P_BF16>, a, grid, st); break;
   }
 }
-void launch_multidot(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_multidot, a, grid, st); }
+void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_dots, a, grid, st); }
 void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update, a, grid, st); }
-void launch_update_r(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_update_r, a, grid, st); }
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_x_update, a, grid, st); }
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(grid), dim3(WG), 0, st, a, v);

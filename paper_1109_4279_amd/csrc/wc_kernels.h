@@ -105,15 +105,14 @@ struct VecLaunch {
 // phi_k = |r| * psi(P)      (psi from the SAP) ; eta(P) = r / |r|
 void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
 void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
-void launch_multidot(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, l < k
-void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);    // chi_k -= sum a_lk chi_l; |chi_k|^2, <chi_k, r>
-void launch_update_r(const VecLaunch& a, int grid, hipStream_t st);     // chi_k /= b_k; r -= c_k chi_k; |r|^2
+void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, <chi_l, r>, |chi_k|^2, <chi_k, r>
+void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);   // chi_k = (chi_k - sum a_lk chi_l)/b_k; r -= c_k chi_k; |r|^2
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials
 void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st);
 
 // per-system reductions and scalar steps (one work-group per system)
-enum ReduceOp { RED_MULTIDOT = 0, RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5 };
+enum ReduceOp { RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5 };
 void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
                    hipStream_t st);
 void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st);
