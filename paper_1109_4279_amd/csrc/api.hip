@@ -328,7 +328,8 @@ static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
 
 static int default_nr(int nrhs, int prec, bool sap) {
   if (nrhs <= 1) return 1;
-  if (sap) return 1;
+  // 16-bit storage: two rhs share the block operator staged in LDS (4^4 blocks)
+  if (sap) return is16(prec) ? 2 : 1;
   // FP64 with four rhs per lane spills; two fit in the register file
   if (prec == P_F64) return 2;
   return nrhs >= 4 ? 4 : nrhs;
@@ -416,7 +417,9 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.write_z = wz;
   a.cache = sap_cache_mode(it.n);
   a.uniform_bvol = B.uniform_bvol;
-  if (split)
+  if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
+    launch_sap_mr_lds(prec, nr, a, persistent_grid(it.n, 1), st);
+  else if (split)
     launch_sap_mr3(prec, a, persistent_grid(it.n, 2), ((3 * B.max_bvol + 63) / 64) * 64, B.max_bvol,
                    B.uniform_bvol, st);
   else

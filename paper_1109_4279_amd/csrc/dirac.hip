@@ -65,28 +65,30 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
       bool same;
       // forward: (1 - gamma_mu) U_mu(x) psi(x + mu)
       int nf = neighbour(g, s, tile, tc, lc, MU, +1, &ph, &same);
+      // 16-bit storage: links and spinors are used unscaled and the site scales folded
+      // into the one weight of the hop
       if (!a.block || same) {
-        SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, s);
-        const R w8 = R(ph);
+        SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, s);
+        const R w8 = R(ph) * LinkIO<P>::scale(L.gscale, s);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p = SpinorIO<P>::load(fin[r], nf);
+          Spinor<R> p = SpinorIO<P>::load_raw(fin[r], nf);
           if (a.dagger) g5(p);
           Half<R> h = mul_U(u, project<R, MU, -1>(p));
-          accum_recon<R, MU, -1>(acc[r], h, w8);
+          accum_recon<R, MU, -1>(acc[r], h, w8 * SpinorIO<P>::scale(fin[r], nf));
         }
       }
       // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
       int nb = neighbour(g, s, tile, tc, lc, MU, -1, &ph, &same);
       if (!a.block || same) {
-        SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, nb);
-        const R w8 = R(ph);
+        SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, nb);
+        const R w8 = R(ph) * LinkIO<P>::scale(L.gscale, nb);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p = SpinorIO<P>::load(fin[r], nb);
+          Spinor<R> p = SpinorIO<P>::load_raw(fin[r], nb);
           if (a.dagger) g5(p);
           Half<R> h = mul_Udag(u, project<R, MU, +1>(p));
-          accum_recon<R, MU, +1>(acc[r], h, w8);
+          accum_recon<R, MU, +1>(acc[r], h, w8 * SpinorIO<P>::scale(fin[r], nb));
         }
       }
     };
@@ -97,24 +99,28 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
 
     // clover and the -1/2 of the hopping term; acc becomes the result
     Spinor<R> self[NR];
+    R sself[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      self[r] = SpinorIO<P>::load(fin[r], s);
+      self[r] = SpinorIO<P>::load_raw(fin[r], s);
+      sself[r] = SpinorIO<P>::scale(fin[r], s);
       if (a.dagger) g5(self[r]);
     }
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      Herm6<R> hc = CloverIO<P>::load(L.clov, L.cscale, g.V, s, blk);
+      Herm6<R> hc = CloverIO<P>::load_raw(L.clov, L.cscale, g.V, s, blk);
+      const R cs = CloverIO<P>::scale(L.cscale, s, blk);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         cplx<R> v[6], o[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) v[i] = self[r].c[2 * blk + i / 3][i % 3];
         herm6_apply(hc, v, o);
+        const R w = cs * sself[r];
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
           cplx<R>& t = acc[r].c[2 * blk + i / 3][i % 3];
-          t = o[i] - R(0.5) * t;
+          t = w * o[i] - R(0.5) * t;
         }
       }
     }

@@ -69,20 +69,22 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
         bool same;
         int nf = neighbour(g, s, tile, tc, lc, MU, +1, &ph, &same);
         if (!same) {
-          SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, s);
+          SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, s);
+          const R w = R(0.5) * R(ph) * LinkIO<P>::scale(L.gscale, s);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            Spinor<R> p = SpinorIO<P>::load(fz[r], nf);
-            accum_recon<R, MU, -1>(rho[r], mul_U(u, project<R, MU, -1>(p)), R(0.5) * R(ph));
+            Spinor<R> p = SpinorIO<P>::load_raw(fz[r], nf);
+            accum_recon<R, MU, -1>(rho[r], mul_U(u, project<R, MU, -1>(p)), w * SpinorIO<P>::scale(fz[r], nf));
           }
         }
         int nb = neighbour(g, s, tile, tc, lc, MU, -1, &ph, &same);
         if (!same) {
-          SU3<R> u = LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, nb);
+          SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, nb);
+          const R w = R(0.5) * R(ph) * LinkIO<P>::scale(L.gscale, nb);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            Spinor<R> p = SpinorIO<P>::load(fz[r], nb);
-            accum_recon<R, MU, +1>(rho[r], mul_Udag(u, project<R, MU, +1>(p)), R(0.5) * R(ph));
+            Spinor<R> p = SpinorIO<P>::load_raw(fz[r], nb);
+            accum_recon<R, MU, +1>(rho[r], mul_Udag(u, project<R, MU, +1>(p)), w * SpinorIO<P>::scale(fz[r], nb));
           }
         }
       };
@@ -134,24 +136,27 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
           constexpr int MU = decltype(MUc)::value;
           if (inf[MU]) {
             const int ln = nfw[MU] - tile * bvol;
-            SU3<R> u = CACHE ? Uf[CACHE ? MU : 0] : LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, s);
+            // uncached 16-bit links are used unscaled, the scale joins the hop weight
+            SU3<R> u = CACHE ? Uf[CACHE ? MU : 0] : LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, s);
+            const R w = R(-0.5) * (CACHE ? R(phf[MU]) : R(phf[MU]) * LinkIO<P>::scale(L.gscale, s));
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               Spinor<R> p;
 #pragma unroll
               for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * bvol + ln];
-              accum_recon<R, MU, -1>(q[r], mul_U(u, project<R, MU, -1>(p)), R(phf[MU]));
+              accum_recon<R, MU, -1>(q[r], mul_U(u, project<R, MU, -1>(p)), w);
             }
           }
           if (inb[MU]) {
             const int ln = nbw[MU] - tile * bvol;
-            SU3<R> u = CACHE ? Ub[CACHE ? MU : 0] : LinkIO<P>::load(L.gauge, L.gscale, g.V, MU, nbw[MU]);
+            SU3<R> u = CACHE ? Ub[CACHE ? MU : 0] : LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, nbw[MU]);
+            const R w = R(-0.5) * (CACHE ? R(phb[MU]) : R(phb[MU]) * LinkIO<P>::scale(L.gscale, nbw[MU]));
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               Spinor<R> p;
 #pragma unroll
               for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * bvol + ln];
-              accum_recon<R, MU, +1>(q[r], mul_Udag(u, project<R, MU, +1>(p)), R(phb[MU]));
+              accum_recon<R, MU, +1>(q[r], mul_Udag(u, project<R, MU, +1>(p)), w);
             }
           }
         };
@@ -161,7 +166,8 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
         hop(std::integral_constant<int, 3>());
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
-          Herm6<R> hc = CACHE ? Cl[CACHE ? blk : 0] : CloverIO<P>::load(L.clov, L.cscale, g.V, s, blk);
+          Herm6<R> hc = CACHE ? Cl[CACHE ? blk : 0] : CloverIO<P>::load_raw(L.clov, L.cscale, g.V, s, blk);
+          const R cs = CACHE ? R(1) : CloverIO<P>::scale(L.cscale, s, blk);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             cplx<R> v[6], o[6];
@@ -169,9 +175,9 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
             for (int i = 0; i < 6; ++i) v[i] = rho[r].c[2 * blk + i / 3][i % 3];
             herm6_apply(hc, v, o);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
+            for (int i = 0; i < 6; ++i) {  // q holds -1/2 of the hops already
               cplx<R>& x = q[r].c[2 * blk + i / 3][i % 3];
-              x = o[i] - R(0.5) * x;
+              x = x + cs * o[i];
             }
           }
         }

@@ -70,6 +70,8 @@ template <> struct SpinorIO<P_F64> {
     for (int k = 0; k < 12; ++k) p[(size_t)k * f.V] = make_double2(o.c[k / 3][k % 3].re, o.c[k / 3][k % 3].im);
   }
   static constexpr int bytes_per_site = 192;
+  static WC_D Spinor<double> load_raw(const FieldRef& f, int s) { return load(f, s); }
+  static WC_D double scale(const FieldRef&, int) { return 1.0; }
 };
 
 template <> struct SpinorIO<P_F32> {
@@ -96,10 +98,29 @@ template <> struct SpinorIO<P_F32> {
     }
   }
   static constexpr int bytes_per_site = 96;
+  static WC_D Spinor<float> load_raw(const FieldRef& f, int s) { return load(f, s); }
+  static WC_D float scale(const FieldRef&, int) { return 1.f; }
 };
 
 template <int P> struct SpinorIO16 {
   typedef float R;
+  // values without the site scale (multiply by scale() to get the field)
+  static WC_D Spinor<float> load_raw(const FieldRef& f, int s) {
+    const uint4* p = (const uint4*)f.d + s;
+    Spinor<float> o;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint4 v = p[(size_t)k * f.V];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int c = 4 * k + j;
+        o.c[c / 3][c % 3] = {s16_to_f32<P>(uint16_t(w[j] & 0xFFFFu)), s16_to_f32<P>(uint16_t(w[j] >> 16))};
+      }
+    }
+    return o;
+  }
+  static WC_D float scale(const FieldRef& f, int s) { return f.sc[s]; }
   static WC_D Spinor<float> load(const FieldRef& f, int s) {
     const uint4* p = (const uint4*)f.d + s;
     float sc = f.sc[s];
@@ -151,6 +172,8 @@ WC_HD int spinor_site_bytes(int P) { return P == P_F64 ? 192 : (P == P_F32 ? 96 
 template <int P> struct LinkIO;
 
 template <> struct LinkIO<P_F64> {
+  static WC_D double scale(const float*, int) { return 1.0; }
+  static WC_D SU3<double> load_raw(const void* g, const float* sc, int V, int mu, int s) { return load(g, sc, V, mu, s); }
   static WC_D SU3<double> load(const void* g, const float*, int V, int mu, int s) {
     const double2* p = (const double2*)g + (size_t)mu * 9 * V + s;
     SU3<double> u;
@@ -163,6 +186,8 @@ template <> struct LinkIO<P_F64> {
   }
 };
 template <> struct LinkIO<P_F32> {
+  static WC_D float scale(const float*, int) { return 1.f; }
+  static WC_D SU3<float> load_raw(const void* g, const float* sc, int V, int mu, int s) { return load(g, sc, V, mu, s); }
   static WC_D SU3<float> load(const void* g, const float*, int V, int mu, int s) {
     const float2* p = (const float2*)g + (size_t)mu * 9 * V + s;
     SU3<float> u;
@@ -175,6 +200,19 @@ template <> struct LinkIO<P_F32> {
   }
 };
 template <int P> struct LinkIO16 {
+  static WC_D float scale(const float* sc, int s) { return sc[s]; }
+  // link without the site scale
+  static WC_D SU3<float> load_raw(const void* g, const float*, int V, int mu, int s) {
+    const uint4* p = (const uint4*)g + (size_t)mu * 2 * V + s;
+    const uint32_t* q = (const uint32_t*)((const uint4*)g + (size_t)8 * V) + (size_t)mu * V + s;
+    uint4 a = p[0], b = p[V];
+    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, *q};
+    SU3<float> u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+      u.m[k / 3][k % 3] = {s16_to_f32<P>(uint16_t(w[k] & 0xFFFFu)), s16_to_f32<P>(uint16_t(w[k] >> 16))};
+    return u;
+  }
   static WC_D SU3<float> load(const void* g, const float* sc, int V, int mu, int s) {
     const uint4* p = (const uint4*)g + (size_t)mu * 2 * V + s;
     const uint32_t* q = (const uint32_t*)((const uint4*)g + (size_t)8 * V) + (size_t)mu * V + s;
@@ -204,6 +242,8 @@ template <class R> struct Herm6 {
 template <int P> struct CloverIO;
 
 template <> struct CloverIO<P_F64> {
+  static WC_D double scale(const float*, int, int) { return 1.0; }
+  static WC_D Herm6<double> load_raw(const void* c, const float* sc, int V, int s, int blk) { return load(c, sc, V, s, blk); }
   static WC_D Herm6<double> load(const void* c, const float*, int V, int s, int blk) {
     const double2* p = (const double2*)c + (size_t)(18 * blk) * V + s;
     Herm6<double> h;
@@ -222,6 +262,8 @@ template <> struct CloverIO<P_F64> {
   }
 };
 template <> struct CloverIO<P_F32> {
+  static WC_D float scale(const float*, int, int) { return 1.f; }
+  static WC_D Herm6<float> load_raw(const void* c, const float* sc, int V, int s, int blk) { return load(c, sc, V, s, blk); }
   static WC_D Herm6<float> load(const void* c, const float*, int V, int s, int blk) {
     const float4* p = (const float4*)c + (size_t)(9 * blk) * V + s;
     float r[36];
@@ -239,10 +281,16 @@ template <> struct CloverIO<P_F32> {
   }
 };
 template <int P> struct CloverIO16 {
-  // 72 halves per site in 9 uint4; reals 36*blk .. 36*blk+35 belong to block blk
+  static WC_D float scale(const float* sc, int s, int blk) { return sc[2 * s + blk]; }
+  static WC_D Herm6<float> load_raw(const void* c, const float*, int V, int s, int blk) {
+    return load_impl(c, 1.f, V, s, blk);
+  }
   static WC_D Herm6<float> load(const void* c, const float* sc, int V, int s, int blk) {
+    return load_impl(c, sc[2 * s + blk], V, s, blk);
+  }
+  // 72 halves per site in 9 uint4; reals 36*blk .. 36*blk+35 belong to block blk
+  static WC_D Herm6<float> load_impl(const void* c, float f, int V, int s, int blk) {
     const uint4* p = (const uint4*)c + s;
-    float f = sc[2 * s + blk];
     float r[36];
     // block 0 uses uint4 0..4 (reals 0..39), block 1 uses uint4 4..8 (reals 32..71)
     const int k0 = blk == 0 ? 0 : 4;
