@@ -8,8 +8,10 @@ cycles, restart 16, one Gaussian source), inputs resident on the device.
 `value` is the sustained solver throughput in Gflop/s (nominal flops of every kernel of
 the solve divided by the step time).  Beside it: the FP64-method solve time on the same
 system, D_w GB/s and Gflop/s per storage precision against the 8 TB/s HBM roofline, the
-roofline record of the dominant kernel (the Schwarz block solver), and the FP64 oracle
-timed on the host for a bounded sample of the same workload.
+roofline record of the dominant kernel (the Schwarz block solver, bound by vector ALU),
+the batched 12-point-source solve on 24^3 x 48 against 12 single FP64-method solves, the
+32^3 x 64 solve on 16-bit storage, and the FP64 oracle timed on the host for a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -29,6 +31,9 @@ M0, CSW = -0.1, 1.0
 NKV, NCY, NMR, TOL = 16, 5, 4, 1e-10
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+# FP32 FMA rate of the kernels as built (no packed FP32 instructions): 256 CUs x 4 SIMDs
+# x 16 lanes x 2 flop x 2.4 GHz
+FP32_SCALAR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # algorithmic bytes per site of one D_w application: spinor in + out, 4 links, 2 clover blocks
 DW_BYTES = {"f64": 192 + 192 + 576 + 576, "f32": 96 + 96 + 288 + 288, "f16": 52 + 52 + 148 + 152,
@@ -88,26 +93,155 @@ def cpu_baseline(U, b):
             "seconds": t, "iters_done": res.iters}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs (profiles/traffic_16c32.json), or None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_16c32.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_1109_4279_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    if rec.get("csrc_sha256") != h.hexdigest() or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes_per_launch"]
+
+
+def timed_solve(lat, b, params, torch):
+    lat.solve(b, params)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = lat.solve(b, params)
+    torch.cuda.synchronize()
+    return x, st, (time.perf_counter() - t0) * 1e3
+
+
+def extra_workloads(wc, torch, dev):
+    """Batched 12-point-source solve on 24^3 x 48 (FP32 arithmetic on FP16 storage) against
+    12 single FP64-method solves, and the 32^3 x 64 single-rhs solve on 16-bit storage."""
+    import synth
+    out = {}
+    dims = (48, 24, 24, 24)
+    lat = wc.Lattice(torch.from_numpy(synth.gauge_field(dims)).to(dev), block=BLOCK, m0=M0, csw=CSW)
+    pts = torch.from_numpy(synth.point_sources(dims)).to(dev)
+    plain = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f64")
+    lat.solve(pts[0].contiguous(), plain)  # warm-up: buffers and graph of the single solve
+    torch.cuda.synchronize()
+    t_single = 0.0
+    iters_single = []
+    for r in range(12):
+        src = pts[r].contiguous()
+        t0 = time.perf_counter()
+        _, st1 = lat.solve(src, plain)
+        torch.cuda.synchronize()
+        t_single += (time.perf_counter() - t0) * 1e3 / 12
+        iters_single.append(st1[0]["iters"])
+    batched = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f16")
+    xb, stb, t_batch = timed_solve(lat, pts, batched, torch)
+    res = max(s["rel_true_res"] for s in stb)
+    out["batch_24c48_12rhs"] = {
+        "fp64_single_rhs_ms": t_single, "mixed_f16_batched_12rhs_ms": t_batch,
+        "speedup_per_rhs": 12 * t_single / t_batch, "iters_batched": max(s["iters"] for s in stb),
+        "iters_fp64": max(iters_single), "max_true_rel_residual": res, "target": 3.0}
+    del lat, pts, xb
+    dims = (64, 32, 32, 32)
+    lat = wc.Lattice(torch.from_numpy(synth.gauge_field(dims)).to(dev), block=BLOCK, m0=M0, csw=CSW)
+    b = torch.from_numpy(synth.gaussian_spinor(dims)).to(dev)
+    rec = {}
+    x64, st64, t64 = timed_solve(lat, b, plain, torch)
+    rec["fp64_ms"], rec["fp64_iters"] = t64, st64[0]["iters"]
+    for sp in ("f32", "f16", "bf16"):
+        x, st, t = timed_solve(lat, b, wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec=sp), torch)
+        rel = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
+        rec[sp] = {"ms": t, "iters": st[0]["iters"], "true_rel_residual": st[0]["rel_true_res"],
+                   "rel_err_vs_fp64_solution": rel}
+    out["solve_32c64"] = rec
+    return out
+
+
+def summarise_pmc(fetch_csv, write_csv, out_json):
+    """Turn two rocprofv3 --pmc runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE)
+    into HBM bytes per launch per kernel.  The counters are scaled by what they read for the
+    run's 1 GiB device copy (1 GiB read, 1 GiB written)."""
+    import csv
+    import hashlib
+
+    def per_kernel(path, name):
+        # the last 20 dispatches of each kernel: the final timing replay of its benchmark loop,
+        # i.e. the launch variant whose duration bench.py reports
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        agg = {}
+        for r in rows:
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return agg
+
+    fetch_all, write_all = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    gib = float(1 << 30)
+    # the 1 GiB copy is the largest copyBuffer dispatch of the run
+    copy_f = max((v for k, vs in fetch_all.items() if "copyBuffer" in k for v in vs), default=gib)
+    copy_w = max((v for k, vs in write_all.items() if "copyBuffer" in k for v in vs), default=gib)
+    fetch = {k: v[-20:] for k, v in fetch_all.items()}
+    write = {k: v[-20:] for k, v in write_all.items()}
+    cf, cw = gib / copy_f, gib / copy_w
+    src = os.path.join(ROOT, "paper_1109_4279_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    kernels = {}
+    for k in fetch:
+        if "wc::" not in k or k not in write:
+            continue
+        short = k.replace("void ", "").replace("wc::", "").split("(")[0]
+        fb = cf * sum(fetch[k]) / len(fetch[k])
+        wb = cw * sum(write[k]) / len(write[k])
+        kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                          "launches": len(fetch[k])}
+    rec = {"csrc_sha256": h.hexdigest(), "fetch_scale": cf, "write_scale": cw,
+           "command": "rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -- python bench.py --profile "
+                      "--steps 2 --warmup 1", "kernels": kernels}
+    json.dump(rec, open(out_json, "w"), indent=1)
+    return rec
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
+        summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--profile", action="store_true", help="short run for profilers: no CPU leg, few kernels")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 24^3x48 batch and 32^3x64 workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding design is "
               "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1109_4279_amd as wc
     import synth
 
     dev = torch.device("cuda:0")
+    if args.profile:
+        # known-size copy (1 GiB read + 1 GiB written) that calibrates the FETCH_SIZE /
+        # WRITE_SIZE counters of a profiled run
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     U_np = synth.gauge_field(DIMS)
     b_np = synth.gaussian_spinor(DIMS)
     U = torch.from_numpy(U_np).to(dev)
@@ -151,17 +285,22 @@ def main():
         gbs = DW_BYTES[prec] * V / (ms * 1e-3) / 1e9
         dw[prec] = {"ms": ms, "GB/s": gbs, "Gflop/s": DW_FLOPS * V / (ms * 1e-3) / 1e9,
                     "frac_hbm": gbs / HBM_PEAK_GBS}
-    # dominant kernel of the step: the FP32 Schwarz half-sweep
+    # dominant kernel of the step: the FP32 Schwarz half-sweep (one colour, 4 MR steps)
     ms_sap = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, iters=20 if args.profile else 100)
     sites = V // 2
     sap_bytes = SAP_BYTES_F32 * sites
     sap_flops = (NMR * (DW_FLOPS + MR_VEC_FLOPS) + BORDER_FLOPS_4444 + 24) * sites
-    ach = sap_bytes / (ms_sap * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "kernel": "k_sap_mr<F32,1> (one colour, 4^4 blocks)",
-                "launch_ms": ms_sap, "alg_bytes_per_launch": sap_bytes,
-                "tflops": sap_flops / (ms_sap * 1e-3) / 1e12,
-                "frac_fp32_peak": sap_flops / (ms_sap * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    tf = sap_flops / (ms_sap * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": tf, "peak": FP32_SCALAR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP32_SCALAR_PEAK_TFLOPS, "traffic": measured_traffic("k_sap_mr<1, 1, true, 256>"),
+                "kernel": "k_sap_mr<F32, 1 rhs, cached, 4^4> (one colour of 16^3x32)",
+                "launch_ms": ms_sap, "alg_flops_per_launch": sap_flops, "alg_bytes_per_launch": sap_bytes,
+                "hbm_GBps_alg": sap_bytes / (ms_sap * 1e-3) / 1e9,
+                "frac_of_packed_fp32_peak": tf / FP32_PEAK_TFLOPS}
+
+    extras = {}
+    if not args.profile and not args.no_extras:
+        extras = extra_workloads(wc, torch, dev)
 
     cpu = None
     if not args.no_cpu and not args.profile:
@@ -192,6 +331,7 @@ def main():
         "dirac": dw,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 
