@@ -346,6 +346,19 @@ static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested) {
 
 // ---------------------------------------------------------------------------- kernels on a batch
 
+// Tile staging of the D_w input needs 256-site tiles in every lattice of the batch.  It
+// pays for FP64 (whose spinors overflow L2 between the nine reads of each) and costs for
+// FP32 / 16-bit (measured on MI355X); WC_DIRAC_STAGE=0/1 forces it off/on where allowed.
+static int dirac_stage_mode(const Batch& B, int prec) {
+  static int forced = -2;
+  if (forced == -2) {
+    const char* e = getenv("WC_DIRAC_STAGE");
+    forced = e ? atoi(e) : -1;
+  }
+  if (B.uniform_bvol != 256) return 0;
+  return forced >= 0 ? forced : (prec == P_F64 ? 1 : 0);
+}
+
 static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, const Field* y, double* partials,
                       const int* skip, int dagger, int block, hipStream_t st) {
   const LatDesc* L = B.lats(prec, st);
@@ -365,6 +378,7 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   a.skip = skip;
   a.dagger = dagger;
   a.block = block;
+  a.stage = dirac_stage_mode(B, prec);
   launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
 }
 

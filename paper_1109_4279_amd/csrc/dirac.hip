@@ -22,10 +22,16 @@ template <class R> WC_D void g5(Spinor<R>& p) {
   }
 }
 
-template <int P, int NR>
+// STAGE: every work item is one 256-site tile (Schwarz blocks of 256 sites); the tile's
+// input spinors are decoded once into LDS and the in-tile neighbours are read from there,
+// so each spinor leaves HBM/L2 once per tile instead of once per neighbour.
+template <int P, int NR, bool STAGE>
 __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
   typedef typename Real<P>::T R;
   __shared__ double red[(WG / 64) * NR];
+  extern __shared__ double stage_d[];
+  cplx<R>* st_sp = (cplx<R>*)stage_d;        // [NR][12][WG] input spinors of the tile (unscaled)
+  R* st_sc = (R*)(st_sp + NR * 12 * WG);     // [NR][WG] their site scales
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     const WorkItem w = a.items[xcd_remap(it0, a.nitems)];
     const LatDesc& L = a.lats[w.lat];
@@ -58,6 +64,30 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
     Spinor<R> acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) zero(acc[r]);
+    if (STAGE) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        Spinor<R> p = SpinorIO<P>::load_raw(fin[r], s);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) st_sp[(r * 12 + k) * WG + threadIdx.x] = p.c[k / 3][k % 3];
+        st_sc[r * WG + threadIdx.x] = SpinorIO<P>::scale(fin[r], s);
+      }
+      __syncthreads();
+    }
+    // input spinor r at site n: from the staged tile when n is in it, else from memory
+    auto in_raw = [&](int r, int n, bool in_tile, R& sc) {
+      Spinor<R> p;
+      if (STAGE && in_tile) {
+        const int ln = n - tile * WG;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = st_sp[(r * 12 + k) * WG + ln];
+        sc = st_sc[r * WG + ln];
+      } else {
+        p = SpinorIO<P>::load_raw(fin[r], n);
+        sc = SpinorIO<P>::scale(fin[r], n);
+      }
+      return p;
+    };
 
     auto hop = [&](auto MUc) {
       constexpr int MU = decltype(MUc)::value;
@@ -72,10 +102,11 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
         const R w8 = R(ph) * LinkIO<P>::scale(L.gscale, s);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p = SpinorIO<P>::load_raw(fin[r], nf);
+          R sc;
+          Spinor<R> p = in_raw(r, nf, same, sc);
           if (a.dagger) g5(p);
           Half<R> h = mul_U(u, project<R, MU, -1>(p));
-          accum_recon<R, MU, -1>(acc[r], h, w8 * SpinorIO<P>::scale(fin[r], nf));
+          accum_recon<R, MU, -1>(acc[r], h, w8 * sc);
         }
       }
       // backward: (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)
@@ -85,10 +116,11 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
         const R w8 = R(ph) * LinkIO<P>::scale(L.gscale, nb);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p = SpinorIO<P>::load_raw(fin[r], nb);
+          R sc;
+          Spinor<R> p = in_raw(r, nb, same, sc);
           if (a.dagger) g5(p);
           Half<R> h = mul_Udag(u, project<R, MU, +1>(p));
-          accum_recon<R, MU, +1>(acc[r], h, w8 * SpinorIO<P>::scale(fin[r], nb));
+          accum_recon<R, MU, +1>(acc[r], h, w8 * sc);
         }
       }
     };
@@ -102,8 +134,7 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
     R sself[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      self[r] = SpinorIO<P>::load_raw(fin[r], s);
-      sself[r] = SpinorIO<P>::scale(fin[r], s);
+      self[r] = in_raw(r, s, true, sself[r]);
       if (a.dagger) g5(self[r]);
     }
 #pragma unroll
@@ -158,17 +189,28 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
       }
       __syncthreads();
     }
+    if (STAGE) __syncthreads();  // the next item overwrites the staged tile
+  }
+}
+
+template <int P, bool S>
+static void launch_ps(const DiracLaunch& a, int nr, int grid, hipStream_t st) {
+  typedef typename Real<P>::T R;
+  auto lds = [&](int n) { return S ? (sizeof(cplx<R>) * 12 + sizeof(R)) * n * WG : 0; };
+  switch (nr) {
+    case 1: hipLaunchKernelGGL((k_dirac<P, 1, S>), dim3(grid), dim3(WG), lds(1), st, a); break;
+    case 2: hipLaunchKernelGGL((k_dirac<P, 2, S>), dim3(grid), dim3(WG), lds(2), st, a); break;
+    case 3: hipLaunchKernelGGL((k_dirac<P, 3, S>), dim3(grid), dim3(WG), lds(3), st, a); break;
+    default: hipLaunchKernelGGL((k_dirac<P, 4, S>), dim3(grid), dim3(WG), lds(4), st, a); break;
   }
 }
 
 template <int P>
 static void launch_p(const DiracLaunch& a, int nr, int grid, hipStream_t st) {
-  switch (nr) {
-    case 1: hipLaunchKernelGGL((k_dirac<P, 1>), dim3(grid), dim3(WG), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_dirac<P, 2>), dim3(grid), dim3(WG), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((k_dirac<P, 3>), dim3(grid), dim3(WG), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_dirac<P, 4>), dim3(grid), dim3(WG), 0, st, a); break;
-  }
+  if (a.stage)
+    launch_ps<P, true>(a, nr, grid, st);
+  else
+    launch_ps<P, false>(a, nr, grid, st);
 }
 
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st) {

@@ -23,6 +23,7 @@ struct DiracLaunch {
   const int* skip;     // if set: systems with skip != 0 are not written
   int dagger;          // apply gamma5 D gamma5
   int block;           // Dirichlet-block operator instead of the full one
+  int stage;           // every lattice has 256-site tiles: stage each tile's input in LDS
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
 
