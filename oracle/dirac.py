@@ -73,6 +73,13 @@ def block_colour(dims, block) -> np.ndarray:
     return (x // np.asarray(block)).sum(axis=-1) % 2
 
 
+def site_parity(dims) -> np.ndarray:
+    """Parity of each site, (x0 + x1 + x2 + x3) mod 2: 0 = even, 1 = odd.  Every
+    nearest-neighbour hop inside a block joins an even and an odd site, since no block
+    wraps around the lattice (the block count per axis is even)."""
+    return coords(dims).sum(axis=-1) % 2
+
+
 def same_block_mask(dims, block, mu: int, step: int) -> np.ndarray:
     """True where the neighbour x + step*mu_hat (periodic) lies in the same block as x."""
     bid = block_index(dims, block)
@@ -160,6 +167,11 @@ def clover_matrix(U: np.ndarray, m0: float, csw: float) -> np.ndarray:
     return A
 
 
+def clover_inverse(A: np.ndarray) -> np.ndarray:
+    """A(x)^-1 per site (the even/odd block solver needs it on the odd sites)."""
+    return np.linalg.inv(A)
+
+
 def chiral_blocks(A: np.ndarray) -> tuple:
     """The two 6x6 diagonal blocks of A in the chiral basis: spins (0, 1) and (2, 3)."""
     return A[..., :6, :6], A[..., 6:, 6:]
@@ -190,6 +202,14 @@ def hop_terms(U: np.ndarray, psi: np.ndarray, bc_t: int = 1, block=None):
             fwd = fwd * same_block_mask(dims, block, mu, +1)[..., None, None]
             bwd = bwd * same_block_mask(dims, block, mu, -1)[..., None, None]
         yield mu, fwd, bwd
+
+
+def apply_hop(U: np.ndarray, psi: np.ndarray, bc_t: int = 1, block=None) -> np.ndarray:
+    """The hopping part of D: -1/2 sum_mu [forward + backward] (D = A + apply_hop)."""
+    out = np.zeros_like(psi)
+    for _, fwd, bwd in hop_terms(U, psi, bc_t, block):
+        out = out - 0.5 * (fwd + bwd)
+    return out
 
 
 def apply_D(U: np.ndarray, A: np.ndarray, psi: np.ndarray, bc_t: int = 1, block=None) -> np.ndarray:

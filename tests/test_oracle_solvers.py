@@ -64,8 +64,83 @@ def test_mr_properties(small):
     assert np.abs(z2 - (2.5 - 1j) * z1).max() < 1e-13 * np.abs(z2).max()
 
 
+# Even/odd block solver: blocks of even volume (2x2x2x1) and of odd volume (3x3x1x1, where
+# the even/odd split of a block depends on the parity of its corner).
+EO_GEOMS = [((4, 4, 4, 2), (2, 2, 2, 1)), ((6, 6, 2, 2), (3, 3, 1, 1))]
+
+
+@pytest.mark.parametrize("bc_t", [1, -1])
+@pytest.mark.parametrize("colour", [0, 1])
+@pytest.mark.parametrize("geom", EO_GEOMS)
+def test_mr_eo_matches_dense_schur(geom, bc_t, colour):
+    """Per block: partition the dense Dirichlet block matrix by site parity, form the Schur
+    complement with library inverses, run textbook MR on it and rebuild the odd half."""
+    dims, block = geom
+    U = synth.gauge_field(dims)
+    A = dirac.clover_matrix(U, -0.1, 1.0)
+    eta = synth.gaussian_spinor(dims, seed=21)
+    z, rho = solvers.mr_blocks_eo(U, A, eta, block, colour, 5, bc_t)
+    MB = dense.assemble(U, A, bc_t, block=block)
+    bid = dirac.block_index(dims, block).ravel()
+    col = dirac.block_colour(dims, block).ravel()
+    par = dirac.coords(dims).sum(-1).ravel() % 2
+    zf, rf, ef = z.reshape(-1, 12), rho.reshape(-1, 12), eta.reshape(-1, 12)
+    rows = lambda s: (s[:, None] * 12 + np.arange(12)).ravel()
+    nblk = 0
+    for b in np.unique(bid):
+        sites = np.nonzero(bid == b)[0]
+        if col[sites[0]] != colour:
+            assert np.abs(zf[sites]).max() == 0 and np.abs(rf[sites]).max() == 0
+            continue
+        nblk += 1
+        e, o = sites[par[sites] == 0], sites[par[sites] == 1]
+        re_, ro = rows(e), rows(o)
+        Mee, Meo = MB[np.ix_(re_, re_)], MB[np.ix_(re_, ro)]
+        Moe, Moo = MB[np.ix_(ro, re_)], MB[np.ix_(ro, ro)]
+        Moo_inv = np.linalg.inv(Moo)
+        S = Mee - Meo @ Moo_inv @ Moe
+        eta_e, eta_o = ef[e].ravel(), ef[o].ravel()
+        ze, res = _textbook_mr(S, eta_e - Meo @ Moo_inv @ eta_o, 5)
+        zo = Moo_inv @ (eta_o - Moe @ ze)
+        scale = np.abs(ef).max()
+        assert np.abs(zf[e].ravel() - ze).max() < 1e-13 * np.abs(ze).max()
+        assert np.abs(zf[o].ravel() - zo).max() < 1e-13 * np.abs(zo).max()
+        assert np.abs(rf[e].ravel() - res).max() < 1e-13 * scale
+        assert np.abs(rf[o]).max() == 0
+    assert nblk > 0
+
+
+@pytest.mark.parametrize("bc_t", [1, -1])
+def test_mr_eo_residual_is_block_residual(bc_t):
+    """rho returned by the even/odd solver is eta - D_Lambda z on the solved blocks."""
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    U = synth.gauge_field(dims)
+    A = dirac.clover_matrix(U, -0.1, 1.0)
+    eta = synth.gaussian_spinor(dims, seed=22)
+    for colour in (0, 1):
+        z, rho = solvers.mr_blocks_eo(U, A, eta, block, colour, 3, bc_t)
+        on = (dirac.block_colour(dims, block) == colour)[..., None, None]
+        want = np.where(on, eta - dirac.apply_D(U, A, z, bc_t, block), 0)
+        assert np.abs(rho - want).max() < 1e-13 * np.abs(eta).max()
+    # zero steps: z is the odd-site part of the exact solve with z_e = 0
+    z0, rho0 = solvers.mr_blocks_eo(U, A, eta, block, 0, 0, bc_t)
+    par = dirac.site_parity(dims)[..., None, None]
+    assert np.abs(np.where(par == 0, z0, 0)).max() == 0
+
+
+def test_mr_eo_beats_plain_mr(small):
+    """At equal step count the Schur-complement iteration leaves a smaller block residual."""
+    U, A = small
+    eta = synth.gaussian_spinor(DIMS, seed=23)
+    for nmr in (1, 2, 4):
+        _, r_plain = solvers.mr_blocks(U, A, eta, BLOCK, 0, nmr)
+        _, r_eo = solvers.mr_blocks_eo(U, A, eta, BLOCK, 0, nmr)
+        assert dirac.norm(r_eo) < dirac.norm(r_plain)
+
+
+@pytest.mark.parametrize("eo", [False, True])
 @pytest.mark.parametrize("ncy", [1, 3])
-def test_sap_exact_block_solves_closed_form(small, ncy):
+def test_sap_exact_block_solves_closed_form(small, ncy, eo):
     """With MR run to convergence the SAP error propagator is [(1 - K1 D)(1 - K0 D)]^ncy with
     K_c the sum over colour-c blocks of the exact inverse Dirichlet block operators."""
     U, A = small
@@ -81,7 +156,7 @@ def test_sap_exact_block_solves_closed_form(small, ncy):
     E = (np.eye(n) - K[1] @ M) @ (np.eye(n) - K[0] @ M)
     eta = synth.gaussian_spinor(DIMS, seed=13)
     want = (np.eye(n) - np.linalg.matrix_power(E, ncy)) @ np.linalg.solve(M, eta.ravel())
-    got = solvers.sap(U, A, eta, BLOCK, nmr=60, ncy=ncy).ravel()
+    got = solvers.sap(U, A, eta, BLOCK, nmr=60, ncy=ncy, eo=eo).ravel()
     assert np.abs(got - want).max() < 1e-11 * np.abs(want).max()
 
 
@@ -93,14 +168,15 @@ def test_sap_is_a_good_preconditioner(small):
     assert dirac.norm(res) < 0.2 * dirac.norm(eta)
 
 
-def test_fgcr_matches_dense_lu_4444():
+@pytest.mark.parametrize("eo", [False, True])
+def test_fgcr_matches_dense_lu_4444(eo):
     """The smallest workload: 4^4, m0 = 0, c_sw = 1, 2^4 blocks, 4 MR steps x 5 SAP cycles,
     FGCR restart 8, tol 1e-10.  The answer must be the dense direct solve's within cond * tol."""
     dims = (4, 4, 4, 4)
     U = synth.gauge_field(dims)
     A = dirac.clover_matrix(U, 0.0, 1.0)
     b = synth.gaussian_spinor(dims)
-    res = solvers.sap_fgcr(U, A, b, (2, 2, 2, 2), nmr=4, ncy=5, nkv=8, tol=1e-10)
+    res = solvers.sap_fgcr(U, A, b, (2, 2, 2, 2), nmr=4, ncy=5, nkv=8, tol=1e-10, eo=eo)
     assert res.converged
     r = b - dirac.apply_D(U, A, res.x)
     assert dirac.norm(r) / dirac.norm(b) <= 1e-10
