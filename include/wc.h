@@ -70,6 +70,7 @@ typedef struct {
   int use_graph; /* 1: replay each restart cycle as one captured hipGraph */
   int nr_dirac;  /* right-hand sides per lane in D (0: library / autotuned choice) */
   int nr_sap;    /* right-hand sides per work-group in the block solver (0: library choice) */
+  int eo;        /* 1: even/odd-preconditioned block solver (Sec. 4, Table 1), 0: MR on D_Lambda */
 } wc_solver_params;
 
 typedef struct {
@@ -110,12 +111,19 @@ int wc_apply_D(wc_ctx* ctx, void* out, const void* in, int nrhs, int prec, int r
 
 /* One Schwarz half-sweep (Sec. 4): nmr MR steps from a zero start on every block of the
  * given colour, source rho.  On return z holds the block solutions on that colour and 0
- * elsewhere; rho holds the MR residual on that colour and 0 elsewhere. */
-int wc_sap_block_mr(wc_ctx* ctx, void* z, void* rho, int nrhs, int colour, int nmr, int prec, void* stream);
+ * elsewhere; rho holds the block residual rho - D_Lambda z on that colour and 0 elsewhere.
+ * eo = 0: MR on the Dirichlet block operator D_Lambda.  eo = 1: the even/odd-preconditioned
+ * block solver (Sec. 4, Table 1): with the block's sites split by parity (sum of the
+ * coordinates mod 2) and H the in-block hops, MR on S = A_ee - H_eo A_oo^-1 H_oe for the
+ * even half, source eta_e - H_eo A_oo^-1 eta_o; then z_o = A_oo^-1 (eta_o - H_oe z_e).  The
+ * block residual is then zero on the odd sites.  The first eo call on a context builds
+ * A^-1 on the odd sites (FP64 Gauss-Jordan, then the storage precision). */
+int wc_sap_block_mr(wc_ctx* ctx, void* z, void* rho, int nrhs, int colour, int nmr, int prec, int eo, void* stream);
 
 /* psi = M_SAP eta: ncy cycles of the Schwarz alternating procedure from psi = 0 (Sec. 4):
- * white blocks, residual update on their neighbours' borders, black blocks, update. */
-int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, void* stream);
+ * white blocks, residual update on their neighbours' borders, black blocks, update.
+ * eo selects the block solver as for wc_sap_block_mr. */
+int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, int eo, void* stream);
 
 /* Solve D x = b for nrhs right-hand sides with SAP-preconditioned restarted FGCR (Sec. 4).
  * The preconditioner runs in p->sap_prec; chi = D phi, Gram-Schmidt, the residual update,
@@ -144,8 +152,8 @@ int wc_link_grad(wc_ctx* ctx, void* G, const void* Y, const void* X, int nrhs, d
 int wc_force(wc_ctx* ctx, void* F, const void* phi, const wc_solver_params* p, wc_solver_stats* st, void* Y,
              void* X, void* stream);
 
-/* Autotune: time the RHS tile of D and of the block solver for (nrhs, prec) and keep the
- * fastest in the context; nr_out[0..1] receive the chosen (D, SAP) tiles. */
+/* Autotune: time the RHS tile of D and of both block solvers for (nrhs, prec) and keep the
+ * fastest in the context; nr_out[0..1] receive the chosen (D, plain block solver) tiles. */
 int wc_autotune(wc_ctx* ctx, int nrhs, int prec, int nr_out[2], void* stream);
 
 /* Choose the Schwarz block shape of the context among the valid shapes with at most 256
@@ -157,7 +165,7 @@ int wc_autotune_block(wc_ctx* ctx, const wc_solver_params* p, int block_out[4], 
  * times back to back on internal fields between two HIP events on `stream`; *ms gets the
  * mean time per launch.  Synchronises `stream`. */
 int wc_bench_dirac(wc_ctx* ctx, int prec, int nrhs, int region, int iters, double* ms, void* stream);
-int wc_bench_sap(wc_ctx* ctx, int prec, int nrhs, int nmr, int iters, double* ms, void* stream);
+int wc_bench_sap(wc_ctx* ctx, int prec, int nrhs, int nmr, int eo, int iters, double* ms, void* stream);
 
 /* Release everything the context owns. */
 void wc_destroy(wc_ctx* ctx);

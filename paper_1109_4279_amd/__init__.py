@@ -112,20 +112,21 @@ class Lattice:
         _lib.check(_lib.load().wc_clover_export(self._ctx, _ptr(A), _stream(stream)))
         return A
 
-    def sap_block_mr(self, rho, colour, nmr, prec="f64", stream=None):
-        """One half-sweep: returns (z, rho_new) as the library computes them (rho is not modified)."""
+    def sap_block_mr(self, rho, colour, nmr, prec="f64", eo=False, stream=None):
+        """One half-sweep: returns (z, rho_new) as the library computes them (rho is not modified).
+        eo selects the even/odd-preconditioned block solver."""
         nrhs = self._spinor(rho, "rho")
         r = rho.clone()
         z = self.new_spinor(None if rho.dim() == 6 else nrhs)
         _lib.check(_lib.load().wc_sap_block_mr(self._ctx, _ptr(z), _ptr(r), nrhs, int(colour), int(nmr), PREC[prec],
-                                               _stream(stream)))
+                                               int(bool(eo)), _stream(stream)))
         return z, r
 
-    def sap(self, eta, ncy=5, nmr=4, prec="f64", stream=None):
+    def sap(self, eta, ncy=5, nmr=4, prec="f64", eo=False, stream=None):
         nrhs = self._spinor(eta, "eta")
         psi = self.new_spinor(None if eta.dim() == 6 else nrhs)
         _lib.check(_lib.load().wc_sap(self._ctx, _ptr(psi), _ptr(eta), nrhs, int(ncy), int(nmr), PREC[prec],
-                                      _stream(stream)))
+                                      int(bool(eo)), _stream(stream)))
         return psi
 
     def solve(self, b, params: SolverParams | None = None, x0=None, stream=None, check=True, **kw):
@@ -191,10 +192,10 @@ class Lattice:
                                               ctypes.byref(ms), _stream(stream)))
         return ms.value
 
-    def bench_sap(self, prec="f32", nrhs=1, nmr=4, iters=20, stream=None):
+    def bench_sap(self, prec="f32", nrhs=1, nmr=4, iters=20, eo=False, stream=None):
         ms = ctypes.c_double()
-        _lib.check(_lib.load().wc_bench_sap(self._ctx, PREC[prec], int(nrhs), int(nmr), int(iters), ctypes.byref(ms),
-                                            _stream(stream)))
+        _lib.check(_lib.load().wc_bench_sap(self._ctx, PREC[prec], int(nrhs), int(nmr), int(bool(eo)), int(iters),
+                                            ctypes.byref(ms), _stream(stream)))
         return ms.value
 
 

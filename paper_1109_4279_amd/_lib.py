@@ -21,6 +21,7 @@ class SolverParams(ctypes.Structure):
         ("nkv", ctypes.c_int), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
         ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("x0_given", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("nr_dirac", ctypes.c_int), ("nr_sap", ctypes.c_int),
+        ("eo", ctypes.c_int),
     ]
 
 
@@ -50,8 +51,8 @@ _SIGS = {
     "wc_set_block": (_I, [_P, ctypes.POINTER(_I), _P]),
     "wc_clover_export": (_I, [_P, _P, _P]),
     "wc_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
-    "wc_sap_block_mr": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
-    "wc_sap": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
+    "wc_sap_block_mr": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),
+    "wc_sap": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),
     "wc_fgcr_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P]),
     "wc_fgcr_solve_batch": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                  ctypes.POINTER(_I), ctypes.POINTER(SolverParams),
@@ -61,7 +62,7 @@ _SIGS = {
     "wc_autotune": (_I, [_P, _I, _I, ctypes.POINTER(_I), _P]),
     "wc_autotune_block": (_I, [_P, ctypes.POINTER(SolverParams), ctypes.POINTER(_I), _P]),
     "wc_bench_dirac": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_D), _P]),
-    "wc_bench_sap": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_D), _P]),
+    "wc_bench_sap": (_I, [_P, _I, _I, _I, _I, _I, ctypes.POINTER(_D), _P]),
     "wc_destroy": (None, [_P]),
     "wc_last_error": (ctypes.c_char_p, []),
     "wc_version": (_I, []),

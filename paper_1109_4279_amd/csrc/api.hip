@@ -147,9 +147,13 @@ struct wc_ctx {
   bool have_links[4] = {false, false, false, false};
   wc::DevBuf clov[4], cscale[4];
   bool have_clov[4] = {false, false, false, false};
+  wc::DevBuf clov_eo[4], cscale_eo[4];  // even/odd block solver: A on even, A^-1 on odd sites
+  bool have_clov_eo[4] = {false, false, false, false};
   wc::DevBuf tiles[2];
+  wc::DevBuf eo_sites;                    // [corner parity][site parity][(bvol+1)/2] local indices
   int nr_dirac[4] = {0, 0, 0, 0};
   int nr_sap[4] = {0, 0, 0, 0};
+  int nr_sap_eo[4] = {0, 0, 0, 0};
   std::map<int, std::unique_ptr<wc::Batch>> batches;  // single-lattice batches by nrhs
   hipStream_t cap = nullptr;                           // capture stream for graphs
   ~wc_ctx();
@@ -176,6 +180,24 @@ static void ensure_clover(wc_ctx* c, int prec, hipStream_t st) {
   c->have_clov[prec] = true;
 }
 
+static void ensure_clover_eo(wc_ctx* c, int prec, hipStream_t st) {
+  require(c->have_clover, WC_ERR_STATE, "clover term not created (call wc_create_clover)");
+  if (c->have_clov_eo[prec]) return;
+  if (!c->have_clov_eo[P_F64]) {
+    c->clov_eo[P_F64].ensure((size_t)c->g.V * clover_site_bytes(P_F64));
+    launch_clover_eo(c->g, c->clov[P_F64].p, c->clov_eo[P_F64].p, st);
+    HIPCK(hipGetLastError());
+    c->have_clov_eo[P_F64] = true;
+  }
+  if (prec != P_F64) {
+    c->clov_eo[prec].ensure((size_t)c->g.V * clover_site_bytes(prec));
+    if (is16(prec)) c->cscale_eo[prec].ensure(sizeof(float) * 2 * c->g.V);
+    launch_clover_convert(prec, c->g, c->clov_eo[P_F64].p, c->clov_eo[prec].p, c->cscale_eo[prec].as<float>(), st);
+    HIPCK(hipGetLastError());
+    c->have_clov_eo[prec] = true;
+  }
+}
+
 // ---------------------------------------------------------------------------- batches
 
 struct ItemList {
@@ -194,6 +216,7 @@ struct Batch {
   std::vector<LatDesc> h_lats[4];
   DevBuf d_lats[4];
   bool have_lats[4] = {false, false, false, false};
+  bool lats_eo[4] = {false, false, false, false};  // descriptors carry the even/odd clover
   std::map<int, ItemList> dirac_items;      // by RHS tile
   std::map<int, ItemList> sap_items[2];     // by RHS tile
   DevBuf sys_part, sys_nchunks;
@@ -244,10 +267,11 @@ struct Batch {
     partials.ensure(sizeof(double) * (size_t)total_chunks * pw);
   }
 
-  const LatDesc* lats(int prec, hipStream_t st) {
-    bool stale = !have_lats[prec];
+  const LatDesc* lats(int prec, hipStream_t st, bool eo = false) {
+    bool stale = !have_lats[prec] || (eo && !lats_eo[prec]);
     for (auto* c : lat) stale |= !c->have_links[prec] || !c->have_clov[prec];
     if (!stale) return d_lats[prec].as<LatDesc>();
+    eo = eo || lats_eo[prec];
     h_lats[prec].clear();
     long long foff = 0;
     int sys0 = 0, part0 = 0;
@@ -268,6 +292,14 @@ struct Batch {
       L.nchunks = (c->g.V + WG - 1) / WG;
       L.tiles[0] = c->tiles[0].as<int>();
       L.tiles[1] = c->tiles[1].as<int>();
+      L.clov_eo = nullptr;
+      L.cscale_eo = nullptr;
+      L.eo_sites = c->eo_sites.as<short>();
+      if (eo) {
+        ensure_clover_eo(c, prec, st);
+        L.clov_eo = c->clov_eo[prec].p;
+        L.cscale_eo = c->cscale_eo[prec].as<float>();
+      }
       h_lats[prec].push_back(L);
       foff += (long long)nrhs[i] * c->g.V;
       sys0 += nrhs[i];
@@ -276,6 +308,7 @@ struct Batch {
     d_lats[prec].ensure(sizeof(LatDesc) * lat.size());
     HIPCK(hipMemcpy(d_lats[prec].p, h_lats[prec].data(), sizeof(LatDesc) * lat.size(), hipMemcpyHostToDevice));
     have_lats[prec] = true;
+    lats_eo[prec] = eo;
     return d_lats[prec].as<LatDesc>();
   }
 
@@ -326,8 +359,10 @@ static Batch& ctx_batch(wc_ctx* c, int nrhs) {
 
 static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
 
-static int default_nr(int nrhs, int prec, bool sap) {
+static int default_nr(int nrhs, int prec, bool sap, int eo) {
   if (nrhs <= 1) return 1;
+  // even/odd block solver: each lane holds two sites, one rhs per work-group
+  if (sap && eo) return 1;
   // 16-bit storage: two rhs share the block operator staged in LDS (4^4 blocks)
   if (sap) return is16(prec) ? 2 : 1;
   // FP64 with four rhs per lane spills; two fit in the register file
@@ -335,9 +370,9 @@ static int default_nr(int nrhs, int prec, bool sap) {
   return nrhs >= 4 ? 4 : nrhs;
 }
 
-static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested) {
-  int nr = requested > 0 ? requested : (sap ? c->nr_sap[prec] : c->nr_dirac[prec]);
-  if (nr <= 0) nr = default_nr(nrhs, prec, sap);
+static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested, int eo = 0) {
+  int nr = requested > 0 ? requested : (sap ? (eo ? c->nr_sap_eo[prec] : c->nr_sap[prec]) : c->nr_dirac[prec]);
+  if (nr <= 0) nr = default_nr(nrhs, prec, sap, eo);
   nr = std::min(nr, 4);
   // block-solver tiles keep the LDS exchange buffer within 64 KB: FP64 one rhs, else two
   if (sap) nr = std::min(nr, prec == P_F64 ? 1 : 2);
@@ -406,11 +441,12 @@ static bool sap_colour_split(int prec, int nr) {
 }
 
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
-                              const int* skip, int first, int border, int wrho, int wz, hipStream_t st) {
+                              const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
-  require(sap_lds_bytes(prec, nr, B.sap_threads()) <= 65536, WC_ERR_GEOMETRY, "block too large for LDS");
+  require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
+          WC_ERR_GEOMETRY, "block too large for LDS");
   const bool split = sap_colour_split(prec, nr);
-  const LatDesc* L = B.lats(prec, st);
+  const LatDesc* L = B.lats(prec, st, eo != 0);
   const ItemList& it = B.items_sap(colour, nr);
   SapLaunch a;
   a.lats = L;
@@ -431,7 +467,9 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.write_z = wz;
   a.cache = sap_cache_mode(it.n);
   a.uniform_bvol = B.uniform_bvol;
-  if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
+  if (eo)
+    launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), B.max_bvol, st);
+  else if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
     launch_sap_mr_lds(prec, nr, a, persistent_grid(it.n, 1), st);
   else if (split)
     launch_sap_mr3(prec, a, persistent_grid(it.n, 2), ((3 * B.max_bvol + 63) / 64) * 64, B.max_bvol,
@@ -442,12 +480,12 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
 
 // ncy Schwarz cycles on rho (source), accumulating psi
 static void run_sap(Batch& B, int prec, int nr, int ncy, int nmr, Field& rho, Field& z, Field& psi, const int* skip,
-                    hipStream_t st) {
+                    int eo, hipStream_t st) {
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
       const bool last = (cy == ncy - 1);
       run_sap_halfsweep(B, prec, nr, c, nmr, rho, z, psi, skip, cy == 0, !(cy == 0 && c == 0), !last,
-                        !(last && c == 1), st);
+                        !(last && c == 1), eo, st);
     }
 }
 
@@ -474,7 +512,7 @@ static void unpack_batch(Batch& B, int prec, const Field& f, void* const* canon,
 // ---------------------------------------------------------------------------- FGCR
 
 struct SolveSetup {
-  int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit;
+  int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit, eo;
   double tol;
 };
 
@@ -523,7 +561,7 @@ static void prepare_solver(Batch& B, const SolveSetup& s) {
   B.skip.ensure(sizeof(int) * B.nsys);
   // everything a captured cycle touches must exist before capture starts
   B.lats(P_F64, nullptr);
-  B.lats(s.sap_prec, nullptr);
+  B.lats(s.sap_prec, nullptr, s.eo != 0);
   B.items_dirac(1);
   B.items_dirac(s.nr_d);
   B.items_sap(0, s.nr_s);
@@ -543,7 +581,7 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
     vs.sp = B.sap_rho.data();
     vs.sp_sc = B.sap_rho.scale();
     launch_to_sap(s.sap_prec, vs, gv, st);
-    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.sap_psi, skip, st);
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.sap_psi, skip, s.eo, st);
     vs.sp = B.sap_psi.data();
     vs.sp_sc = B.sap_psi.scale();
     launch_from_sap(s.sap_prec, vs, gv, st);
@@ -564,8 +602,8 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
 
 static std::string setup_key(const SolveSetup& s) {
   char buf[160];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s, s.maxit,
-           s.tol);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s,
+           s.maxit, s.eo, s.tol);
   return buf;
 }
 
@@ -660,6 +698,7 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   require(p.ncy >= 1 && p.nmr >= 1, WC_ERR_ARG, "ncy and nmr must be >= 1");
   require(p.sap_prec >= 0 && p.sap_prec <= 3, WC_ERR_ARG, "bad sap_prec");
   require(p.tol > 0 && p.maxit >= 1, WC_ERR_ARG, "tol must be > 0 and maxit >= 1");
+  require(p.eo == 0 || p.eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
   SolveSetup s;
   s.nkv = p.nkv;
   s.ncy = p.ncy;
@@ -667,8 +706,9 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   s.sap_prec = p.sap_prec;
   s.tol = p.tol;
   s.maxit = p.maxit;
+  s.eo = p.eo ? 1 : 0;
   s.nr_d = pick_nr(c, max_nrhs, P_F64, false, p.nr_dirac);
-  s.nr_s = pick_nr(c, max_nrhs, p.sap_prec, true, p.nr_sap);
+  s.nr_s = pick_nr(c, max_nrhs, p.sap_prec, true, p.nr_sap, s.eo);
   return s;
 }
 
@@ -710,9 +750,24 @@ static void layout(wc_ctx* c, const int* block, hipStream_t st) {
   c->tiles[1].ensure(sizeof(int) * t1.size());
   HIPCK(hipMemcpy(c->tiles[0].p, t0.data(), sizeof(int) * t0.size(), hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(c->tiles[1].p, t1.data(), sizeof(int) * t1.size(), hipMemcpyHostToDevice));
+  // even and odd sites of a tile in local order, for both parities of the tile's corner
+  const int nh = (c->g.bvol + 1) / 2;
+  std::vector<short> lut(4 * (size_t)nh, (short)-1);
+  for (int cp = 0; cp < 2; ++cp) {
+    int cnt[2] = {0, 0};
+    for (int l = 0; l < c->g.bvol; ++l) {
+      int lc[4];
+      local_coords(c->g, l, lc);
+      const int par = (cp + lc[0] + lc[1] + lc[2] + lc[3]) & 1;
+      lut[(size_t)(2 * cp + par) * nh + cnt[par]++] = (short)l;
+    }
+  }
+  c->eo_sites.ensure(sizeof(short) * lut.size());
+  HIPCK(hipMemcpy(c->eo_sites.p, lut.data(), sizeof(short) * lut.size(), hipMemcpyHostToDevice));
   for (int p = 0; p < 4; ++p) {
     c->have_links[p] = false;
     c->have_clov[p] = false;
+    c->have_clov_eo[p] = false;
   }
   ensure_links(c, P_F64, st);
   if (c->have_clover) {
@@ -746,6 +801,7 @@ void wc_default_params(wc_solver_params* p) {
   p->use_graph = 1;
   p->nr_dirac = 0;
   p->nr_sap = 0;
+  p->eo = 0;
 }
 
 int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const void* U, int bc_t, void* stream) {
@@ -777,7 +833,10 @@ int wc_create_clover(wc_ctx* c, double m0, double csw, void* stream) {
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(S(stream)));
     c->have_clover = true;
-    for (int p = 0; p < 4; ++p) c->have_clov[p] = (p == P_F64);
+    for (int p = 0; p < 4; ++p) {
+      c->have_clov[p] = (p == P_F64);
+      c->have_clov_eo[p] = false;
+    }
     for (auto& kv : c->batches)
       for (int p = 0; p < 4; ++p) kv.second->have_lats[p] = false;
   });
@@ -819,9 +878,10 @@ int wc_apply_D(wc_ctx* c, void* out, const void* in, int nrhs, int prec, int reg
   });
 }
 
-int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr, int prec, void* stream) {
+int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr, int prec, int eo, void* stream) {
   return guarded([&] {
     require(c && z && rho && nrhs >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    require(eo == 0 || eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
     require(colour == 0 || colour == 1, WC_ERR_ARG, "colour must be 0 or 1");
     check_prec(prec);
     require(c->have_clover, WC_ERR_STATE, "clover term not created");
@@ -832,8 +892,8 @@ int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr
     B.sap_psi.ensure(prec, B.sites_rhs);
     const void* ins[1] = {rho};
     pack_batch(B, prec, ins, B.sap_rho, st);
-    run_sap_halfsweep(B, prec, pick_nr(c, nrhs, prec, true, 0), colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr,
-                      1, 0, 1, 1, st);
+    run_sap_halfsweep(B, prec, pick_nr(c, nrhs, prec, true, 0, eo), colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr,
+                      1, 0, 1, 1, eo, st);
     void* zo[1] = {z};
     void* ro[1] = {rho};
     unpack_batch(B, prec, B.sap_z, zo, colour, st);
@@ -842,9 +902,10 @@ int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr
   });
 }
 
-int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, void* stream) {
+int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, int eo, void* stream) {
   return guarded([&] {
     require(c && psi && eta && nrhs >= 1 && ncy >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    require(eo == 0 || eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
     check_prec(prec);
     require(c->have_clover, WC_ERR_STATE, "clover term not created");
     hipStream_t st = S(stream);
@@ -854,7 +915,7 @@ int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, in
     B.sap_psi.ensure(prec, B.sites_rhs);
     const void* ins[1] = {eta};
     pack_batch(B, prec, ins, B.sap_rho, st);
-    run_sap(B, prec, pick_nr(c, nrhs, prec, true, 0), ncy, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, st);
+    run_sap(B, prec, pick_nr(c, nrhs, prec, true, 0, eo), ncy, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, eo, st);
     void* outs[1] = {psi};
     unpack_batch(B, prec, B.sap_psi, outs, -1, st);
     HIPCK(hipGetLastError());
@@ -1022,9 +1083,10 @@ int wc_bench_dirac(wc_ctx* c, int prec, int nrhs, int region, int iters, double*
   });
 }
 
-int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int iters, double* ms, void* stream) {
+int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int eo, int iters, double* ms, void* stream) {
   return guarded([&] {
     require(c && ms && nrhs >= 1 && iters >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
+    require(eo == 0 || eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
     check_prec(prec);
     require(c->have_clover, WC_ERR_STATE, "clover term not created");
     hipStream_t st = S(stream);
@@ -1038,10 +1100,12 @@ int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int iters, double* ms, 
       HIPCK(hipMemsetAsync(B.sap_rho.scale(), 0, sizeof(float) * B.sites_rhs, st));
       HIPCK(hipMemsetAsync(B.sap_z.scale(), 0, sizeof(float) * B.sites_rhs, st));
     }
-    const int nr = pick_nr(c, nrhs, prec, true, 0);
+    const int nr = pick_nr(c, nrhs, prec, true, 0, eo);
+    B.lats(prec, st, eo != 0);
+    HIPCK(hipStreamSynchronize(st));
     int colour = 0;
     *ms = time_launches(c, st, iters, [&](hipStream_t s) {
-      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, s);
+      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, eo, s);
       colour ^= 1;
     });
     HIPCK(hipGetLastError());
@@ -1053,8 +1117,8 @@ int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[2], void* stream) {
     require(c && nrhs >= 1, WC_ERR_ARG, "bad argument");
     check_prec(prec);
     const int cands[3] = {1, 2, 4};
-    double best_d = 1e30, best_s = 1e30;
-    int nd = 1, ns = 1;
+    double best_d = 1e30, best_s = 1e30, best_e = 1e30;
+    int nd = 1, ns = 1, ne = 1;
     for (int nr : cands) {
       if (nr > nrhs) continue;
       c->nr_dirac[prec] = nr;
@@ -1064,12 +1128,17 @@ int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[2], void* stream) {
       if (t < best_d) { best_d = t; nd = nr; }
       if (nr > (prec == P_F64 ? 1 : 2)) continue;
       c->nr_sap[prec] = nr;
-      rc = wc_bench_sap(c, prec, nrhs, 4, 10, &t, stream);
+      rc = wc_bench_sap(c, prec, nrhs, 4, 0, 10, &t, stream);
       require(rc == WC_OK, rc, g_last_error);
       if (t < best_s) { best_s = t; ns = nr; }
+      c->nr_sap_eo[prec] = nr;
+      rc = wc_bench_sap(c, prec, nrhs, 4, 1, 10, &t, stream);
+      require(rc == WC_OK, rc, g_last_error);
+      if (t < best_e) { best_e = t; ne = nr; }
     }
     c->nr_dirac[prec] = nd;
     c->nr_sap[prec] = ns;
+    c->nr_sap_eo[prec] = ne;
     if (nr_out) {
       nr_out[0] = nd;
       nr_out[1] = ns;

@@ -287,6 +287,97 @@ void launch_clover_build(const Geom& g, const void* links64, double m0, double c
                      (double2*)clov64);
 }
 
+// Clover field of the even/odd block solver: A(x) on even sites, A(x)^-1 on odd sites
+// (parity = sum of the global coordinates mod 2), FP64, same storage as the clover term.
+// One thread per (site, chiral block).  A 6x6 Hermitian block is inverted by Gauss-Jordan
+// elimination of [A | 1] with partial pivoting (compare-and-swap of rows, so every index
+// is a compile-time constant); the result is re-symmetrised to the stored Hermitian form.
+__global__ __launch_bounds__(WG) void k_clover_eo(Geom g, const double2* c64, double2* out) {
+  const int i = blockIdx.x * WG + threadIdx.x;
+  if (i >= 2 * g.V) return;
+  const int blk = i >= g.V ? 1 : 0;
+  const int s = i - blk * g.V;
+  const int tile = s / g.bvol;
+  int tc[4], lc[4];
+  tile_coords(g, tile, tc);
+  local_coords(g, s - tile * g.bvol, lc);
+  int par = 0;
+  for (int m = 0; m < 4; ++m) par += tc[m] * g.B[m] + lc[m];
+  const double2* src = c64 + (size_t)(18 * blk) * g.V + s;
+  double2* dst = out + (size_t)(18 * blk) * g.V + s;
+  if ((par & 1) == 0) {
+#pragma unroll
+    for (int k = 0; k < 18; ++k) dst[(size_t)k * g.V] = src[(size_t)k * g.V];
+    return;
+  }
+  cplx<double> M[6][12];
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) M[r][c] = {c == r + 6 ? 1.0 : 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double2 v = src[(size_t)k * g.V];
+    M[2 * k][2 * k] = {v.x, 0.0};
+    M[2 * k + 1][2 * k + 1] = {v.y, 0.0};
+  }
+  {
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = r + 1; c < 6; ++c, ++k) {
+        double2 v = src[(size_t)(3 + k) * g.V];
+        M[r][c] = {v.x, v.y};
+        M[c][r] = {v.x, -v.y};
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+#pragma unroll
+    for (int r = k + 1; r < 6; ++r) {
+      const double a = M[r][k].re * M[r][k].re + M[r][k].im * M[r][k].im;
+      const double b = M[k][k].re * M[k][k].re + M[k][k].im * M[k][k].im;
+      const bool sw = a > b;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cplx<double> t = M[k][c];
+        M[k][c] = sw ? M[r][c] : t;
+        M[r][c] = sw ? t : M[r][c];
+      }
+    }
+    const cplx<double> p = M[k][k];
+    const double den = p.re * p.re + p.im * p.im;
+    const cplx<double> inv = {p.re / den, -p.im / den};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) M[k][c] = inv * M[k][c];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      if (r == k) continue;
+      const cplx<double> f = M[r][k];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) M[r][c] = M[r][c] - f * M[k][c];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dst[(size_t)k * g.V] = make_double2(M[2 * k][2 * k + 6].re, M[2 * k + 1][2 * k + 7].re);
+  {
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = r + 1; c < 6; ++c, ++k) {
+        const cplx<double> up = M[r][c + 6], lo = M[c][r + 6];
+        dst[(size_t)(3 + k) * g.V] = make_double2(0.5 * (up.re + lo.re), 0.5 * (up.im - lo.im));
+      }
+  }
+}
+
+void launch_clover_eo(const Geom& g, const void* clov64, void* out64, hipStream_t st) {
+  dim3 grid((2 * g.V + WG - 1) / WG);
+  hipLaunchKernelGGL(k_clover_eo, grid, dim3(WG), 0, st, g, (const double2*)clov64, (double2*)out64);
+}
+
 // FP64 clover (36 double2 per site) -> storage precision
 template <int P>
 __global__ __launch_bounds__(WG) void k_clover_convert(Geom g, const double2* c64, void* dst, float* dst_sc) {

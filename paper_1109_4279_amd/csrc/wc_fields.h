@@ -22,6 +22,10 @@ struct LatDesc {
   int part0;           // offset of this lattice's first reduction partial
   int nchunks;         // ceil(V / WG): partials per system
   const int* tiles[2]; // tile indices of each chessboard colour (ntiles/2 each)
+  // even/odd block solver (null unless it is in use)
+  const void* clov_eo;    // A on even sites, A^-1 on odd sites, storage precision of the launch
+  const float* cscale_eo; // its 16-bit scales [V][2]
+  const short* eo_sites;  // [corner parity][site parity][(bvol+1)/2] tile-local site indices, -1 = none
 };
 
 // A unit of work: WG consecutive sites (or one tile for the Schwarz kernels)

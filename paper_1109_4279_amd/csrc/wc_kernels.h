@@ -54,6 +54,10 @@ size_t sap3_lds_bytes(int bvol);
 // 16-bit storage, 4^4 blocks: block operator staged in LDS and shared by nr (1 or 2) rhs
 void launch_sap_mr_lds(int prec, int nr, const SapLaunch& a, int grid, hipStream_t st);
 
+// even/odd-preconditioned block solver: two lanes per (even site, odd site) pair of a block
+void launch_sap_eo(int prec, int nr, const SapLaunch& a, int grid, int max_bvol, hipStream_t st);
+size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol);
+
 // ----------------------------------------------------------------- layout conversion / setup
 // canonical complex128 [rhs][V][4][3] (lexicographic) <-> internal field of one lattice
 void launch_pack_spinor(int prec, const Geom& g, int nrhs, const void* canon, void* dst, float* dst_sc,
@@ -64,6 +68,8 @@ void launch_unpack_spinor(int prec, const Geom& g, int nrhs, const void* src, co
 void launch_pack_links(int prec, const Geom& g, const void* canon, void* dst, float* dst_sc, hipStream_t st);
 // clover blocks from internal FP64 links, FP64 storage
 void launch_clover_build(const Geom& g, const void* links64, double m0, double csw, void* clov64, hipStream_t st);
+// even/odd block-solver clover: A on even sites, A^-1 on odd sites (FP64 -> FP64)
+void launch_clover_eo(const Geom& g, const void* clov64, void* out64, hipStream_t st);
 // FP64 clover -> storage precision
 void launch_clover_convert(int prec, const Geom& g, const void* clov64, void* dst, float* dst_sc, hipStream_t st);
 

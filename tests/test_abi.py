@@ -35,12 +35,29 @@ def test_library_exports_every_declared_symbol():
     assert lib2.wc_version() == 100
 
 
+def _param_counts():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(wc_[A-Za-z0-9_]+)\s*\(([^)]*)\)\s*;", text):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    from paper_1109_4279_amd import _lib
+    counts = _param_counts()
+    assert set(counts) == set(_declared())
+    for name, (_, args) in _lib._SIGS.items():
+        assert len(args) == counts[name], name
+
+
 def test_default_params_and_error_text():
     from paper_1109_4279_amd import _lib, default_params
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("libwc.so not built")
     p = default_params()
-    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit) == (16, 5, 4, 1, 10000)
+    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo) == (16, 5, 4, 1, 10000, 0)
     assert abs(p.tol - 1e-10) < 1e-25
     lib = _lib.load()
     # argument errors are reported without touching a device
