@@ -2,16 +2,18 @@
 
 One step = one complete mixed-precision solve D x = b to a true FP64 residual of 1e-10
 (FP32 Schwarz preconditioner on FP32 storage, FP64 outer FGCR) on the 16^3 x 32 lattice
-(gauge recipe eps = 0.3, m0 = -0.1, c_sw = 1, 4^4 Schwarz blocks, 4 MR steps, 5 SAP
-cycles, restart 16, one Gaussian source), inputs resident on the device.
+(gauge recipe eps = 0.3, m0 = -0.1, c_sw = 1, 4^4 Schwarz blocks, 4 MR steps of the
+even/odd-preconditioned block solver, 5 SAP cycles, restart 16, one Gaussian source),
+inputs resident on the device.
 
 `value` is the sustained solver throughput in Gflop/s (nominal flops of every kernel of
-the solve divided by the step time).  Beside it: the FP64-method solve time on the same
-system, D_w GB/s and Gflop/s per storage precision against the 8 TB/s HBM roofline, the
-roofline record of the dominant kernel (the Schwarz block solver, bound by vector ALU),
-the batched 12-point-source solve on 24^3 x 48 against 12 single FP64-method solves, the
-32^3 x 64 solve on 16-bit storage, and the FP64 oracle timed on the host for a bounded
-sample of the same workload.
+the solve divided by the step time).  Beside it: the FP64 solve time on the same system
+(with the same block solver and with MR on the unpreconditioned block operator), the
+mixed solve with the unpreconditioned block solver, D_w GB/s and Gflop/s per storage
+precision against the 8 TB/s HBM roofline, the roofline record of the dominant kernel
+(the Schwarz block solver, bound by vector ALU), the batched 12-point-source solve on
+24^3 x 48 against 12 single FP64 solves, the 32^3 x 64 solve on 16-bit storage, and the
+FP64 oracle timed on the host for a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -46,13 +48,23 @@ MR_VEC_FLOPS = 336          # per site and MR step: <q,rho>, <q,q>, z += a rho, 
 BORDER_FLOPS_4444 = 2 * 168  # 2 cross-block hops per site on 4^4 blocks (project + SU(3) + add)
 
 
-def sap_flops_per_site(ncy, nmr):
-    """Nominal flops of one SAP application per lattice site (R22: 1824 per D_Lambda site)."""
-    per_half = nmr * (DW_FLOPS + MR_VEC_FLOPS) + 24
-    return ncy * per_half + (ncy - 0.5) * BORDER_FLOPS_4444
+def half_sweep_flops_per_site(nmr, eo):
+    """Nominal flops of one Schwarz half-sweep per solved site, D_Lambda counted as the full
+    1824 flops of D_w.  Plain block solver: nmr MR steps on D_Lambda.  Even/odd block solver:
+    an application of the Schur complement touches every site of the block once (hops and a
+    6x6 clover pair), the MR vector work runs on the even half, and the source (A_oo^-1,
+    H_eo) and the odd half of the solution (H_oe, A_oo^-1) add one more block sweep."""
+    if eo:
+        return nmr * (DW_FLOPS + MR_VEC_FLOPS / 2) + DW_FLOPS + 24
+    return nmr * (DW_FLOPS + MR_VEC_FLOPS) + 24
 
 
-def solve_flops(V, iters, restarts, nkv, ncy, nmr):
+def sap_flops_per_site(ncy, nmr, eo=False):
+    """Nominal flops of one SAP application per lattice site."""
+    return ncy * half_sweep_flops_per_site(nmr, eo) + (ncy - 0.5) * BORDER_FLOPS_4444
+
+
+def solve_flops(V, iters, restarts, nkv, ncy, nmr, eo=False):
     """Nominal flops of a restarted SAP-FGCR solve with `iters` iterations over `restarts` cycles."""
     f = 0.0
     left = iters
@@ -60,7 +72,7 @@ def solve_flops(V, iters, restarts, nkv, ncy, nmr):
         kd = min(nkv, left)
         left -= kd
         for k in range(kd):
-            f += sap_flops_per_site(ncy, nmr) + 48       # preconditioner + scaling in/out
+            f += sap_flops_per_site(ncy, nmr, eo) + 48   # preconditioner + scaling in/out
             f += DW_FLOPS                                  # chi = D phi (FP64)
             f += 2 * 96 * k + 144 + 168                     # CGS dots + update, norms, r update
         f += 96 * kd + DW_FLOPS + 72                        # x update, true residual
@@ -69,8 +81,8 @@ def solve_flops(V, iters, restarts, nkv, ncy, nmr):
 
 def cpu_baseline(U, b):
     """The FP64 oracle on a bounded sample of the same workload: one FGCR iteration
-    (one SAP application with 4 MR steps x 5 cycles, chi = D phi, Gram-Schmidt) on the
-    16^3 x 32 system, single thread, reported in the same Gflop/s unit."""
+    (one SAP application with 4 even/odd block-solver steps x 5 cycles, chi = D phi,
+    Gram-Schmidt) on the 16^3 x 32 system, single thread, reported in the same Gflop/s unit."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -82,14 +94,15 @@ def cpu_baseline(U, b):
         t_setup = time.perf_counter() - t0
         t0 = time.perf_counter()
         res = solvers.fgcr(lambda v: dirac.apply_D(U, A, v),
-                           lambda v: solvers.sap(U, A, v, BLOCK, NMR, NCY),
+                           lambda v: solvers.sap(U, A, v, BLOCK, NMR, NCY, eo=True),
                            b, tol=1e-300, nkv=NKV, maxit=1)
         t = time.perf_counter() - t0
     V = int(np.prod(DIMS))
-    fl = solve_flops(V, 1, 1, NKV, NCY, NMR)
+    fl = solve_flops(V, 1, 1, NKV, NCY, NMR, eo=True)
     return {"value": fl / t / 1e9, "unit": "Gflop/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FGCR iteration (SAP {NCY} cycles x {NMR} MR + FP64 D + GS + true residual) of the "
-                      f"16^3x32 workload, numpy FP64, 1 thread; {t:.1f} s (clover setup {t_setup:.1f} s not counted)",
+            "sample": f"one FGCR iteration (SAP {NCY} cycles x {NMR} even/odd block-solver steps + FP64 D + GS + "
+                      f"true residual) of the 16^3x32 workload, numpy FP64, 1 thread; {t:.1f} s (clover setup "
+                      f"{t_setup:.1f} s not counted)",
             "seconds": t, "iters_done": res.iters}
 
 
@@ -121,42 +134,55 @@ def timed_solve(lat, b, params, torch):
     return x, st, (time.perf_counter() - t0) * 1e3
 
 
+def params(wc, sap_prec, eo):
+    return wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec=sap_prec, eo=int(eo), use_graph=1)
+
+
+def single_solves(lat, srcs, p, torch):
+    """Mean time per rhs of solving the sources one at a time (after a warm-up solve)."""
+    lat.solve(srcs[0].contiguous(), p)
+    torch.cuda.synchronize()
+    t, iters = 0.0, []
+    for r in range(srcs.shape[0]):
+        src = srcs[r].contiguous()
+        t0 = time.perf_counter()
+        _, st1 = lat.solve(src, p)
+        torch.cuda.synchronize()
+        t += (time.perf_counter() - t0) * 1e3 / srcs.shape[0]
+        iters.append(st1[0]["iters"])
+    return t, max(iters)
+
+
 def extra_workloads(wc, torch, dev):
-    """Batched 12-point-source solve on 24^3 x 48 (FP32 arithmetic on FP16 storage) against
-    12 single FP64-method solves, and the 32^3 x 64 single-rhs solve on 16-bit storage."""
+    """Batched 12-point-source solve on 24^3 x 48 (FP32 arithmetic on FP16 storage, even/odd
+    block solver) against 12 single FP64 solves (with MR on D_Lambda, the plain method, and
+    with the same block solver), and the 32^3 x 64 single-rhs solve on every storage."""
     import synth
     out = {}
     dims = (48, 24, 24, 24)
     lat = wc.Lattice(torch.from_numpy(synth.gauge_field(dims)).to(dev), block=BLOCK, m0=M0, csw=CSW)
     pts = torch.from_numpy(synth.point_sources(dims)).to(dev)
-    plain = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f64")
-    lat.solve(pts[0].contiguous(), plain)  # warm-up: buffers and graph of the single solve
-    torch.cuda.synchronize()
-    t_single = 0.0
-    iters_single = []
-    for r in range(12):
-        src = pts[r].contiguous()
-        t0 = time.perf_counter()
-        _, st1 = lat.solve(src, plain)
-        torch.cuda.synchronize()
-        t_single += (time.perf_counter() - t0) * 1e3 / 12
-        iters_single.append(st1[0]["iters"])
-    batched = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f16")
-    xb, stb, t_batch = timed_solve(lat, pts, batched, torch)
+    t_mr, it_mr = single_solves(lat, pts, params(wc, "f64", False), torch)
+    t_eo, it_eo = single_solves(lat, pts, params(wc, "f64", True), torch)
+    xb, stb, t_batch = timed_solve(lat, pts, params(wc, "f16", True), torch)
     res = max(s["rel_true_res"] for s in stb)
     out["batch_24c48_12rhs"] = {
-        "fp64_single_rhs_ms": t_single, "mixed_f16_batched_12rhs_ms": t_batch,
-        "speedup_per_rhs": 12 * t_single / t_batch, "iters_batched": max(s["iters"] for s in stb),
-        "iters_fp64": max(iters_single), "max_true_rel_residual": res, "target": 3.0}
+        "fp64_single_rhs_ms": t_mr, "fp64_single_rhs_iters": it_mr,
+        "fp64_eo_single_rhs_ms": t_eo, "fp64_eo_single_rhs_iters": it_eo,
+        "mixed_f16_eo_batched_12rhs_ms": t_batch, "iters_batched": max(s["iters"] for s in stb),
+        "speedup_per_rhs": 12 * t_mr / t_batch, "speedup_per_rhs_vs_fp64_eo": 12 * t_eo / t_batch,
+        "max_true_rel_residual": res, "target": 3.0}
     del lat, pts, xb
     dims = (64, 32, 32, 32)
     lat = wc.Lattice(torch.from_numpy(synth.gauge_field(dims)).to(dev), block=BLOCK, m0=M0, csw=CSW)
     b = torch.from_numpy(synth.gaussian_spinor(dims)).to(dev)
     rec = {}
-    x64, st64, t64 = timed_solve(lat, b, plain, torch)
+    _, st_mr, t_mr = timed_solve(lat, b, params(wc, "f64", False), torch)
+    rec["fp64_mr_ms"], rec["fp64_mr_iters"] = t_mr, st_mr[0]["iters"]
+    x64, st64, t64 = timed_solve(lat, b, params(wc, "f64", True), torch)
     rec["fp64_ms"], rec["fp64_iters"] = t64, st64[0]["iters"]
     for sp in ("f32", "f16", "bf16"):
-        x, st, t = timed_solve(lat, b, wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec=sp), torch)
+        x, st, t = timed_solve(lat, b, params(wc, sp, True), torch)
         rel = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
         rec[sp] = {"ms": t, "iters": st[0]["iters"], "true_rel_residual": st[0]["rel_true_res"],
                    "rel_err_vs_fp64_solution": rel}
@@ -248,8 +274,7 @@ def main():
     b = torch.from_numpy(b_np).to(dev)
     lat = wc.Lattice(U, block=BLOCK, m0=M0, csw=CSW)
     V = lat.volume
-    mixed = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f32", use_graph=1)
-    plain = wc.default_params(nkv=NKV, ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f64", use_graph=1)
+    mixed = params(wc, "f32", True)
 
     for _ in range(args.warmup):
         lat.solve(b, mixed)
@@ -266,16 +291,14 @@ def main():
     # the answer, checked with the library's own FP64 operator
     r = b - lat.apply_D(x)
     rel_res = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
-    flops = solve_flops(V, st["iters"], st["restarts"], NKV, NCY, NMR)
+    flops = solve_flops(V, st["iters"], st["restarts"], NKV, NCY, NMR, eo=True)
     value = flops / (ms_per_step * 1e-3) / 1e9
 
-    # the plain FP64 method on the same system
-    lat.solve(b, plain)
-    torch.cuda.synchronize()
-    tp0 = time.perf_counter()
-    x64, st64 = lat.solve(b, plain)
-    torch.cuda.synchronize()
-    tts_fp64 = (time.perf_counter() - tp0) * 1e3
+    # FP64 on the same system with the same block solver and with MR on D_Lambda, and the
+    # mixed solve with MR on D_Lambda
+    x64, st64, tts_fp64 = timed_solve(lat, b, params(wc, "f64", True), torch)
+    _, st64mr, tts_fp64_mr = timed_solve(lat, b, params(wc, "f64", False), torch)
+    _, stmr, tts_mixed_mr = timed_solve(lat, b, params(wc, "f32", False), torch)
     rel_err = (torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64)).item()
 
     # D_w per storage precision (HIP events inside the library, same stream)
@@ -285,18 +308,21 @@ def main():
         gbs = DW_BYTES[prec] * V / (ms * 1e-3) / 1e9
         dw[prec] = {"ms": ms, "GB/s": gbs, "Gflop/s": DW_FLOPS * V / (ms * 1e-3) / 1e9,
                     "frac_hbm": gbs / HBM_PEAK_GBS}
-    # dominant kernel of the step: the FP32 Schwarz half-sweep (one colour, 4 MR steps)
-    ms_sap = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, iters=20 if args.profile else 100)
+    # dominant kernel of the step: the FP32 Schwarz half-sweep (one colour, 4 steps of the
+    # even/odd block solver); the unpreconditioned block solver's half-sweep beside it
+    ms_sap = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, eo=True, iters=20 if args.profile else 100)
+    ms_sap_mr = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, eo=False, iters=20 if args.profile else 100)
     sites = V // 2
     sap_bytes = SAP_BYTES_F32 * sites
-    sap_flops = (NMR * (DW_FLOPS + MR_VEC_FLOPS) + BORDER_FLOPS_4444 + 24) * sites
+    sap_flops = (half_sweep_flops_per_site(NMR, True) + BORDER_FLOPS_4444) * sites
     tf = sap_flops / (ms_sap * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": tf, "peak": FP32_SCALAR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tf / FP32_SCALAR_PEAK_TFLOPS, "traffic": measured_traffic("k_sap_mr<1, 1, true, 256>"),
-                "kernel": "k_sap_mr<F32, 1 rhs, cached, 4^4> (one colour of 16^3x32)",
+                "frac": tf / FP32_SCALAR_PEAK_TFLOPS, "traffic": measured_traffic("k_sap_eo<1, 1, true>"),
+                "kernel": "k_sap_eo<F32, 1 rhs, cached> (one colour of 16^3x32, 4 steps)",
                 "launch_ms": ms_sap, "alg_flops_per_launch": sap_flops, "alg_bytes_per_launch": sap_bytes,
                 "hbm_GBps_alg": sap_bytes / (ms_sap * 1e-3) / 1e9,
-                "frac_of_packed_fp32_peak": tf / FP32_PEAK_TFLOPS}
+                "frac_of_packed_fp32_peak": tf / FP32_PEAK_TFLOPS,
+                "plain_mr_half_sweep_ms": ms_sap_mr}
 
     extras = {}
     if not args.profile and not args.no_extras:
@@ -320,13 +346,17 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "SAP-FGCR solve to 1e-10, 16^3x32, eps=0.3 gauge, m0=-0.1, c_sw=1, "
-                               "blocks 4^4, nmr=4, ncy=5, nkv=16, 1 Gaussian rhs, FP32 SAP / FP64 outer",
+                               "blocks 4^4, nmr=4 (even/odd block solver), ncy=5, nkv=16, 1 Gaussian rhs, "
+                               "FP32 SAP / FP64 outer",
                    "lattice": list(DIMS), "block": list(BLOCK), "parallelism": "single GPU"},
         "tts_mixed_ms": ms_per_step,
         "tts_fp64_ms": tts_fp64,
         "speedup_mixed_vs_fp64": tts_fp64 / ms_per_step,
+        "tts_fp64_mr_ms": tts_fp64_mr,
+        "speedup_mixed_vs_fp64_mr": tts_fp64_mr / ms_per_step,
+        "tts_mixed_mr_ms": tts_mixed_mr,
         "iters_mixed": st["iters"], "restarts_mixed": st["restarts"],
-        "iters_fp64": st64[0]["iters"],
+        "iters_fp64": st64[0]["iters"], "iters_fp64_mr": st64mr[0]["iters"], "iters_mixed_mr": stmr[0]["iters"],
         "true_rel_residual": rel_res, "rel_err_mixed_vs_fp64": rel_err,
         "dirac": dw,
         "roofline": roofline,
