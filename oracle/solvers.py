@@ -172,3 +172,135 @@ def sap_fgcr(U, A, b, block, nmr=4, ncy=5, nkv=16, tol=1e-10, bc_t=1, maxit=1000
         lambda v: apply_D(U, A, v, bc_t),
         lambda v: sap(U, A, v, block, nmr, ncy, bc_t, eo),
         b, tol=tol, nkv=nkv, maxit=maxit)
+
+
+def harmonic_ritz(Hbar: np.ndarray):
+    """Harmonic Ritz pairs of a cycle of m Arnoldi steps (Sec. 4) from the (m+1) x m upper
+    Hessenberg matrix Hbar: with H its top m x m block and h = Hbar[m, m-1], the pairs are
+    the eigenpairs of H + |h|^2 H^-H e_m e_m^T.  Returns (theta, G) with the columns of G
+    the eigenvectors, sorted by increasing |theta|."""
+    m = Hbar.shape[1]
+    H = Hbar[:m, :m]
+    em = np.zeros(m, dtype=np.complex128)
+    em[-1] = 1.0
+    f = np.linalg.solve(H.conj().T, em)
+    Hh = H + abs(Hbar[m, m - 1]) ** 2 * np.outer(f, em)
+    theta, G = np.linalg.eig(Hh)
+    order = np.argsort(np.abs(theta), kind="stable")
+    return theta[order], G[:, order]
+
+
+def _orthonormalise(cols):
+    """Modified Gram-Schmidt on a list of vectors; returns the matrix of orthonormal columns."""
+    out = []
+    for v in cols:
+        w = v.astype(np.complex128).copy()
+        for q in out:
+            w = w - np.vdot(q, w) * q
+        out.append(w / np.linalg.norm(w))
+    return np.stack(out, axis=1)
+
+
+def deflation_basis(Hbar: np.ndarray, s: np.ndarray, k: int):
+    """The (m+1) x (k+1) matrix P of a deflated restart: the k harmonic Ritz vectors of
+    smallest |theta| padded with a zero, then the least-squares residual s, orthonormalised
+    in that order.  Returns (P, theta[:k])."""
+    theta, G = harmonic_ritz(Hbar)
+    cols = [np.append(G[:, i], 0.0) for i in range(k)] + [s]
+    return _orthonormalise(cols), theta[:k]
+
+
+def deflate(V, Z, Hbar, s, k: int):
+    """Restart state from k harmonic Ritz vectors: V <- V P, Z <- Z P[:m, :k],
+    Hbar <- P^H Hbar P[:m, :k], c <- P^H s.  Returns (V, Z, Hbar, c, theta)."""
+    m = Hbar.shape[1]
+    P, theta = deflation_basis(Hbar, s, k)
+    Vn = [sum(P[i, l] * V[i] for i in range(m + 1)) for l in range(k + 1)]
+    Zn = [sum(P[i, l] * Z[i] for i in range(m)) for l in range(k)]
+    return Vn, Zn, P.conj().T @ Hbar @ P[:m, :k], P.conj().T @ s, theta
+
+
+class FGMRESDRResult(FGCRResult):
+    def __init__(self, x, converged, iters, restarts, history, theta):
+        super().__init__(x, converged, iters, restarts, history)
+        self.theta = theta  # harmonic Ritz values kept at the last deflated restart
+
+
+def fgmres_dr(apply_op, precond, b, tol: float = 1e-10, m: int = 16, k: int = 0, maxit: int = 10000, x0=None):
+    """Restarted flexible GMRES with deflated restarts, all in FP64 (Sec. 4: FGMRES-DR, the
+    flexible form of Morgan's GMRES-DR).
+
+    A cycle extends an orthonormal basis v_0.. with a variable preconditioner: z_j = M(v_j),
+    w = A z_j, orthogonalised against every v_i by modified Gram-Schmidt (h_ij = <v_i, w>),
+    h_{j+1,j} = |w|, v_{j+1} = w / h_{j+1,j}; so A Z = V Hbar.  The residual is V c, c its
+    coefficients; the cycle ends after m vectors z or once min_d |c - Hbar d| <= tol |b| / 2.
+    Then x += Z d for the least-squares d and r = b - A x is recomputed; the solve stops when
+    |r| / |b| <= tol.
+
+    Restart: with k = 0 the next cycle starts from v_0 = r / |r| (restarted FGMRES).  With
+    k > 0 the k harmonic Ritz vectors of smallest |theta| (``harmonic_ritz``), padded with a
+    zero, are orthonormalised, the least-squares residual s = c - Hbar d is orthonormalised
+    against them, and these k+1 columns P give the next cycle's start: V <- V P,
+    Z <- Z P[:m, :k], Hbar <- P^H Hbar P[:m, :k], c <- P^H s.  The cycle then extends the
+    basis from k+1 to m+1 vectors."""
+    bnorm = norm(b)
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - apply_op(x) if x0 is not None else b.copy()
+    history = [norm(r) / bnorm]
+    iters = 0
+    restarts = 0
+    theta_kept = None
+    V, Z, Hbar, c = [], [], None, None
+    while True:
+        if history[-1] <= tol:
+            return FGMRESDRResult(x, True, iters, restarts, history, theta_kept)
+        if iters >= maxit:
+            return FGMRESDRResult(x, False, iters, restarts, history, theta_kept)
+        if not V:  # plain start from the residual
+            beta = norm(r)
+            V = [r / beta]
+            Z = []
+            Hbar = np.zeros((1, 0), dtype=np.complex128)
+            c = np.zeros(1, dtype=np.complex128)
+            c[0] = beta
+        d = np.zeros(0, dtype=np.complex128)
+        while len(Z) < m and iters < maxit:
+            j = len(Z)
+            z = precond(V[j])
+            w = apply_op(z)
+            h = np.zeros(j + 2, dtype=np.complex128)
+            for i in range(j + 1):
+                h[i] = dot(V[i], w)
+                w = w - h[i] * V[i]
+            h[j + 1] = norm(w)
+            Z.append(z)
+            V.append(w / h[j + 1])
+            Hn = np.zeros((j + 2, j + 1), dtype=np.complex128)
+            Hn[: j + 1, :j] = Hbar
+            Hn[:, j] = h
+            Hbar = Hn
+            c = np.append(c, 0.0)
+            iters += 1
+            d = np.linalg.lstsq(Hbar, c, rcond=None)[0]
+            if np.linalg.norm(c - Hbar @ d) <= 0.5 * tol * bnorm:
+                break
+        for j in range(len(Z)):
+            x = x + d[j] * Z[j]
+        r = b - apply_op(x)
+        restarts += 1
+        history.append(norm(r) / bnorm)
+        s = c - Hbar @ d
+        mm = len(Z)
+        kk = min(k, mm - 1)
+        if kk <= 0:
+            V = []
+            continue
+        V, Z, Hbar, c, theta_kept = deflate(V, Z, Hbar, s, kk)
+
+
+def sap_fgmres_dr(U, A, b, block, nmr=4, ncy=5, m=16, k=0, tol=1e-10, bc_t=1, maxit=10000, eo=False):
+    """FGMRES-DR with the SAP preconditioner (Sec. 4), all FP64."""
+    return fgmres_dr(
+        lambda v: apply_D(U, A, v, bc_t),
+        lambda v: sap(U, A, v, block, nmr, ncy, bc_t, eo),
+        b, tol=tol, m=m, k=k, maxit=maxit)
