@@ -133,6 +133,23 @@ int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, 
 int wc_fgcr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_solver_params* p, wc_solver_stats* st,
                   void* stream);
 
+/* Solve D x = b with SAP-preconditioned FGMRES-DR (Sec. 4): flexible GMRES cycles of
+ * p->nkv Arnoldi steps (FP64 basis, classical Gram-Schmidt; preconditioner as for
+ * wc_fgcr_solve); at a restart the kdefl harmonic Ritz vectors of the cycle's matrix Hbar
+ * with the smallest |theta| (wc_harmonic_ritz), orthonormalised and augmented with the
+ * least-squares residual, start the next cycle, which then adds nkv - kdefl steps.
+ * kdefl = 0 is restarted FGMRES.  0 <= kdefl < nkv.  The least squares, the harmonic Ritz
+ * pairs and the deflation basis are computed on the host in FP64 at every restart (the
+ * host synchronises `stream` twice per restart); the Arnoldi cycle runs on the device (one
+ * captured hipGraph per first column when p->use_graph).  The basis is orthogonalised by
+ * classical Gram-Schmidt applied twice, since it is carried over restarts.  If any
+ * unconverged rhs ended its cycle with fewer than kdefl + 1 columns, its recomputed FP64
+ * residual exceeds 10x the cycle's least-squares residual, or the small problem is
+ * singular, that restart is taken without deflation, from the true residual.  Stats and errors as wc_fgcr_solve; iters counts Arnoldi
+ * steps (preconditioner applications). */
+int wc_fgmres_dr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_solver_params* p, int kdefl,
+                       wc_solver_stats* st, void* stream);
+
 /* The same for nlat lattices of different sizes solved together: every kernel of the
  * solve is one launch over all lattices and right-hand sides.  x[i], b[i] are the
  * lattice-i arrays with nrhs[i] right-hand sides; st receives sum(nrhs) entries. */
@@ -143,6 +160,14 @@ int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const voi
  * (dL = Re sum tr(G^dag dU)), complex128 [4][L0..L3][3][3].  Hopping and clover terms
  * (product rule over the plaquette leaves).  Used for the backward of D and of D^-1. */
 int wc_link_grad(wc_ctx* ctx, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream);
+
+/* Harmonic Ritz pairs of an Arnoldi cycle (Sec. 4, the deflated restarts of FGMRES-DR),
+ * computed on the host in FP64: eigenpairs of H + |h_{m+1,m}|^2 H^-H e_m e_m^T with H the
+ * top m x m block of the (m+1) x m matrix Hbar.  Hbar: host complex128, column-major with
+ * leading dimension m+1.  theta (m complex128) and G (m x m complex128, column-major,
+ * unit columns) receive the pairs sorted by increasing |theta|.  1 <= m <= 32.
+ * Errors: WC_ERR_ARG, WC_ERR_BREAKDOWN (H singular or no convergence). */
+int wc_harmonic_ritz(int m, const void* Hbar, void* theta, void* G);
 
 /* Pseudofermion force of S = phi^dag (D^dag D)^-1 phi (Sec. 1: the HMC force from the
  * fermion determinant): Y = D^-dag phi and X = D^-1 Y by two solves with p, then

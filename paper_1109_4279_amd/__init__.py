@@ -146,6 +146,26 @@ class Lattice:
             _lib.check(rc)
         return x, stats
 
+    def solve_fgmres_dr(self, b, k=8, params: SolverParams | None = None, x0=None, stream=None, check=True, **kw):
+        """x = D^-1 b by SAP-preconditioned FGMRES-DR: cycles of params.nkv Arnoldi steps, k
+        harmonic Ritz vectors kept at every restart (k = 0: restarted FGMRES).  Returns
+        (x, list of per-rhs stats dicts)."""
+        nrhs = self._spinor(b, "b")
+        p = params if params is not None else default_params(**kw)
+        if x0 is not None:
+            x = x0.clone()
+            p.x0_given = 1
+        else:
+            x = self.new_spinor(None if b.dim() == 6 else nrhs)
+            p.x0_given = 0
+        st = (SolverStats * nrhs)()
+        rc = _lib.load().wc_fgmres_dr_solve(self._ctx, _ptr(x), _ptr(b), nrhs, ctypes.byref(p), int(k), st,
+                                            _stream(stream))
+        stats = [s.as_dict() for s in st]
+        if check:
+            _lib.check(rc)
+        return x, stats
+
     def link_grad(self, Y, X, coef=1.0, stream=None):
         """G with d(sum Re<Y, D X>) = Re sum tr(G^dag dU), times coef (torch gradient convention)."""
         nrhs = self._spinor(X, "X")

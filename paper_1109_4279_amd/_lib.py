@@ -51,6 +51,8 @@ _SIGS = {
     "wc_set_block": (_I, [_P, ctypes.POINTER(_I), _P]),
     "wc_clover_export": (_I, [_P, _P, _P]),
     "wc_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
+    "wc_harmonic_ritz": (_I, [_I, _P, _P, _P]),
+    "wc_fgmres_dr_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolverParams), _I, ctypes.POINTER(SolverStats), _P]),
     "wc_sap_block_mr": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),
     "wc_sap": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),
     "wc_fgcr_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P]),

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/wc.h"
+#include "dense_host.h"
 #include "wc_kernels.h"
 
 namespace wc {
@@ -232,9 +233,15 @@ struct Batch {
   // captured restart cycle
   hipGraphExec_t graph = nullptr;
   std::string graph_key;
+  // FGMRES-DR: the last basis vector V_m, the basis pointer table (m+1 entries), the
+  // per-system cycle state and the captured cycles by (setup, first column)
+  Field arn_vlast;
+  DevBuf d_arn_v, arn;
+  std::map<std::string, hipGraphExec_t> arn_graphs;
 
   ~Batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto& kv : arn_graphs) (void)hipGraphExecDestroy(kv.second);
   }
 
   void init(const std::vector<wc_ctx*>& l, const std::vector<int>& n) {
@@ -535,6 +542,7 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.phi = B.d_phi.as<double2* const>();
   a.sp = nullptr;
   a.sp_sc = nullptr;
+  a.arn = nullptr;
   return a;
 }
 
@@ -712,6 +720,272 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   return s;
 }
 
+// ---------------------------------------------------------------------------- FGMRES-DR
+
+static VecLaunch arn_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
+  VecLaunch a = vec_launch(B, s, st);
+  a.chi = B.d_arn_v.as<double2* const>();
+  a.arn = B.arn.as<ArnState>();
+  return a;
+}
+
+static void prepare_fgmres(Batch& B, const SolveSetup& s) {
+  prepare_solver(B, s);
+  B.arn_vlast.ensure(P_F64, B.sites_rhs);
+  std::vector<double2*> pv(NKV_MAX + 1, nullptr);
+  for (int k = 0; k < s.nkv; ++k) pv[k] = B.chi[k].d.as<double2>();
+  pv[s.nkv] = B.arn_vlast.d.as<double2>();
+  B.d_arn_v.ensure(sizeof(double2*) * (NKV_MAX + 1));
+  HIPCK(hipMemcpy(B.d_arn_v.p, pv.data(), sizeof(double2*) * (NKV_MAX + 1), hipMemcpyHostToDevice));
+  B.arn.ensure(sizeof(ArnState) * B.nsys);
+}
+
+// Arnoldi columns j0 .. m-1 of one cycle; systems whose cycle ended sit out
+static void enqueue_arn_cycle(Batch& B, const SolveSetup& s, int j0, hipStream_t st) {
+  VecLaunch va = arn_launch(B, s, st);
+  const int gv = persistent_grid(va.nitems, 8);
+  const int* skip = B.skip.as<int>();
+  for (int j = j0; j < s.nkv; ++j) {
+    va.k = j;
+    VecLaunch vs = va;
+    vs.sp = B.sap_rho.data();
+    vs.sp_sc = B.sap_rho.scale();
+    launch_arn_to_sap(s.sap_prec, vs, gv, st);
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.sap_psi, skip, s.eo, st);
+    vs.sp = B.sap_psi.data();
+    vs.sp_sc = B.sap_psi.scale();
+    launch_arn_from_sap(s.sap_prec, vs, gv, st);
+    Field& next = (j + 1 < s.nkv) ? B.chi[j + 1] : B.arn_vlast;
+    run_dirac(B, P_F64, s.nr_d, B.phi[j], next, nullptr, nullptr, skip, 0, 0, st);
+    launch_arn_dots(va, gv, st);
+    launch_arn_reduce(1, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), s.nkv, st);
+    launch_arn_update1(va, gv, st);
+    launch_arn_reduce(2, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), s.nkv, st);
+    launch_arn_update(va, gv, st);
+  }
+}
+
+// The deflated restart of one system on the host: P from the k harmonic Ritz vectors of
+// smallest |theta| and the least-squares residual s, the new (k+1) x k matrix P^H Hbar P_k,
+// its Givens factorisation and the new residual coefficients.  Returns false when the
+// small problem is singular (the caller then restarts without deflation).
+static bool deflate_host(int mm, int k, ArnState& A, const std::vector<dense::cd>& sres, std::vector<dense::cd>& cnew) {
+  using dense::cd;
+  const int ld = ARN_LD;
+  std::vector<cd> H((size_t)ld * NKV_MAX);
+  for (int j = 0; j < mm; ++j)
+    for (int i = 0; i <= mm; ++i) H[i + j * ld] = cd(A.H[i + j * ld].x, A.H[i + j * ld].y);
+  std::vector<cd> theta(mm), G((size_t)mm * mm);
+  if (!dense::harmonic_ritz(mm, H.data(), ld, theta.data(), G.data(), mm)) return false;
+  std::vector<cd> P((size_t)ld * ld, cd(0.0));
+  for (int l = 0; l < k; ++l)
+    for (int i = 0; i < mm; ++i) P[i + l * ld] = G[i + l * mm];
+  for (int i = 0; i <= mm; ++i) P[i + k * ld] = sres[i];
+  if (!dense::orthonormalise(mm + 1, k + 1, P.data(), ld)) return false;
+  // Hn = P^H Hbar P[:mm, :k] ; cnew = P^H s
+  std::vector<cd> HP((size_t)ld * k, cd(0.0)), Hn((size_t)ld * k, cd(0.0));
+  for (int l = 0; l < k; ++l)
+    for (int i = 0; i <= mm; ++i) {
+      cd t = 0.0;
+      for (int j = 0; j < mm; ++j) t += H[i + j * ld] * P[j + l * ld];
+      HP[i + l * ld] = t;
+    }
+  for (int l = 0; l < k; ++l)
+    for (int r = 0; r <= k; ++r) {
+      cd t = 0.0;
+      for (int i = 0; i <= mm; ++i) t += std::conj(P[i + r * ld]) * HP[i + l * ld];
+      Hn[r + l * ld] = t;
+    }
+  cnew.assign(k + 1, cd(0.0));
+  for (int r = 0; r <= k; ++r) {
+    cd t = 0.0;
+    for (int i = 0; i <= mm; ++i) t += std::conj(P[i + r * ld]) * sres[i];
+    cnew[r] = t;
+  }
+  // the device state of the next cycle: Hbar = Hn, its rotations and rotated coefficients
+  std::vector<cd> R(Hn), g(cnew);
+  g.resize(ld, cd(0.0));
+  std::vector<dense::Rot> rots;
+  dense::givens_qr(k + 1, k, R.data(), ld, g.data(), rots);
+  if ((int)rots.size() > ARN_ROT_MAX - NKV_MAX - 1) return false;
+  for (int i = 0; i < ld * NKV_MAX; ++i) A.H[i] = make_double2(0.0, 0.0);
+  for (int l = 0; l < k; ++l)
+    for (int r = 0; r <= k; ++r) A.H[r + l * ld] = make_double2(Hn[r + l * ld].real(), Hn[r + l * ld].imag());
+  for (int i = 0; i < ld; ++i) A.g[i] = make_double2(g[i].real(), g[i].imag());
+  A.nrot = (int)rots.size();
+  for (int q = 0; q < A.nrot; ++q) {
+    A.rc[q] = rots[q].c;
+    A.rs[q] = make_double2(rots[q].s.real(), rots[q].s.imag());
+    A.rp[q] = rots[q].p;
+  }
+  for (int i = 0; i < ld * ld; ++i) A.P[i] = make_double2(P[i].real(), P[i].imag());
+  A.pin = mm + 1;
+  A.pout = k + 1;
+  A.lucky = 0;
+  return true;
+}
+
+static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_given, bool use_graph, wc_ctx* cap_owner,
+                           std::vector<wc_solver_stats>& stats, hipStream_t st) {
+  using dense::cd;
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  HIPCK(hipEventRecord(e0, st));
+  VecLaunch va = arn_launch(B, s, st);
+  const int gv = persistent_grid(va.nitems, 8);
+  const int n = B.nsys, m = s.nkv, ld = ARN_LD;
+  launch_norm2(va, B.b.d.as<double2>(), gv, st);
+  launch_reduce(RED_BNORM, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  if (x0_given) {
+    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    launch_reduce(RED_INITR, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  } else {
+    HIPCK(hipMemsetAsync(B.x.data(), 0, spinor_bytes(P_F64, B.sites_rhs), st));
+    launch_copy_f64(va, B.r.d.as<double2>(), B.b.d.as<double2>(), gv, st);
+  }
+  HIPCK(hipGetLastError());
+
+  std::vector<SysState> hs(n);
+  std::vector<ArnState> ha(n);
+  std::vector<std::vector<cd>> cvec(n), sres(n);
+  auto get_sys = [&] {
+    HIPCK(hipMemcpyAsync(hs.data(), B.sys.p, sizeof(SysState) * n, hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+  };
+  auto put_arn = [&] {
+    HIPCK(hipMemcpyAsync(B.arn.p, ha.data(), sizeof(ArnState) * n, hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+  };
+  int j0 = 0;
+  for (int rs = 0; rs <= s.maxit; ++rs) {
+    get_sys();
+    bool all = true;
+    for (const SysState& S : hs) all &= (S.converged != 0);
+    if (all) break;
+    if (j0 == 0) {
+      // a cycle without deflation: V_0 = r / |r|, c = |r| e_0
+      for (int i = 0; i < n; ++i) {
+        ArnState& A = ha[i];
+        A.nrot = 0;
+        A.lucky = 0;
+        A.pin = A.pout = 0;
+        for (int q = 0; q < ld * NKV_MAX; ++q) A.H[q] = make_double2(0.0, 0.0);
+        for (int q = 0; q < ld; ++q) A.g[q] = make_double2(0.0, 0.0);
+        A.g[0] = make_double2(std::sqrt(hs[i].rnorm2), 0.0);
+        cvec[i].assign(1, cd(std::sqrt(hs[i].rnorm2), 0.0));
+      }
+      put_arn();
+      launch_arn_init(va, gv, st);
+    }
+    if (use_graph) {
+      char key[200];
+      snprintf(key, sizeof key, "%s|%d", setup_key(s).c_str(), j0);
+      auto it = B.arn_graphs.find(key);
+      if (it == B.arn_graphs.end()) {
+        if (!cap_owner->cap) HIPCK(hipStreamCreateWithFlags(&cap_owner->cap, hipStreamNonBlocking));
+        HIPCK(hipStreamSynchronize(st));
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        HIPCK(hipStreamBeginCapture(cap_owner->cap, hipStreamCaptureModeThreadLocal));
+        enqueue_arn_cycle(B, s, j0, cap_owner->cap);
+        HIPCK(hipStreamEndCapture(cap_owner->cap, &graph));
+        HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPCK(hipGraphDestroy(graph));
+        it = B.arn_graphs.emplace(key, exec).first;
+      }
+      HIPCK(hipGraphLaunch(it->second, st));
+    } else {
+      enqueue_arn_cycle(B, s, j0, st);
+    }
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(ha.data(), B.arn.p, sizeof(ArnState) * n, hipMemcpyDeviceToHost, st));
+    get_sys();
+    // least squares of every active system: x += Z d
+    for (int i = 0; i < n; ++i) {
+      SysState& S = hs[i];
+      if (S.converged) continue;
+      const int mm = S.k_done;
+      std::vector<cd> H((size_t)ld * NKV_MAX), c(cvec[i]), d(std::max(mm, 1), cd(0.0));
+      c.resize(mm + 1, cd(0.0));
+      for (int j = 0; j < mm; ++j)
+        for (int r = 0; r <= mm; ++r) H[r + j * ld] = cd(ha[i].H[r + j * ld].x, ha[i].H[r + j * ld].y);
+      if (mm == 0 || S.breakdown || !dense::lstsq(mm + 1, mm, H.data(), ld, c.data(), d.data())) {
+        S.breakdown = 1;
+        d.assign(std::max(mm, 1), cd(0.0));
+      }
+      sres[i].assign(mm + 1, cd(0.0));
+      for (int r = 0; r <= mm; ++r) {
+        cd t = c[r];
+        for (int j = 0; j < mm; ++j) t -= H[r + j * ld] * d[j];
+        sres[i][r] = t;
+      }
+      for (int j = 0; j < mm; ++j) S.alpha[j] = make_double2(d[j].real(), d[j].imag());
+    }
+    HIPCK(hipMemcpyAsync(B.sys.p, hs.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, st));
+    HIPCK(hipStreamSynchronize(st));
+    launch_x_update(va, gv, st);
+    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    launch_reduce(RED_TRUE, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+    HIPCK(hipGetLastError());
+    std::vector<int> mm_of(n);
+    for (int i = 0; i < n; ++i) mm_of[i] = hs[i].k_done;
+    get_sys();
+    // next cycle: deflated when every active system has k+1 columns to deflate from and its
+    // recomputed residual still agrees with the cycle's least-squares residual (otherwise
+    // the restart starts afresh from the true residual)
+    bool defl = kdefl > 0;
+    for (int i = 0; i < n; ++i) {
+      if (hs[i].converged) continue;
+      double sn = 0.0;
+      for (const cd& z : sres[i]) sn += std::norm(z);
+      defl = defl && mm_of[i] >= kdefl + 1 && !ha[i].lucky && hs[i].rnorm2 <= 100.0 * sn;
+    }
+    if (defl) {
+      for (int i = 0; i < n && defl; ++i) {
+        if (hs[i].converged) continue;
+        std::vector<cd> cn;
+        defl = deflate_host(mm_of[i], kdefl, ha[i], sres[i], cn);
+        cvec[i] = cn;
+      }
+    }
+    if (defl) {
+      put_arn();
+      launch_arn_recombine(va, gv, st);
+      HIPCK(hipGetLastError());
+      j0 = kdefl;
+    } else {
+      j0 = 0;
+    }
+  }
+  HIPCK(hipEventRecord(e1, st));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  get_sys();
+  int rc = WC_OK;
+  stats.resize(n);
+  for (int i = 0; i < n; ++i) {
+    wc_solver_stats& o = stats[i];
+    const SysState& S = hs[i];
+    o.iters = S.iters;
+    o.restarts = S.restarts;
+    o.breakdown = S.breakdown;
+    o.rel_true_res = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+    o.time_ms = ms;
+    if (S.breakdown)
+      o.status = WC_ERR_BREAKDOWN;
+    else if (S.bnorm2 > 0 && !(S.rnorm2 <= S.tol2))
+      o.status = WC_ERR_NOT_CONVERGED;
+    else
+      o.status = WC_OK;
+    if (rc == WC_OK && o.status != WC_OK) rc = o.status;
+  }
+  return rc;
+}
+
 // ---------------------------------------------------------------------------- helpers for the C interface
 
 static hipStream_t S(void* stream) { return (hipStream_t)stream; }
@@ -878,6 +1152,14 @@ int wc_apply_D(wc_ctx* c, void* out, const void* in, int nrhs, int prec, int reg
   });
 }
 
+int wc_harmonic_ritz(int m, const void* Hbar, void* theta, void* G) {
+  return guarded([&] {
+    require(m >= 1 && m <= NKV_MAX && Hbar && theta && G, WC_ERR_ARG, "bad argument");
+    require(dense::harmonic_ritz(m, (const dense::cd*)Hbar, m + 1, (dense::cd*)theta, (dense::cd*)G, m),
+            WC_ERR_BREAKDOWN, "harmonic Ritz pairs: singular H or no convergence");
+  });
+}
+
 int wc_sap_block_mr(wc_ctx* c, void* z, void* rho, int nrhs, int colour, int nmr, int prec, int eo, void* stream) {
   return guarded([&] {
     require(c && z && rho && nrhs >= 1 && nmr >= 0, WC_ERR_ARG, "bad argument");
@@ -922,9 +1204,10 @@ int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, in
   });
 }
 
+// kdefl < 0: FGCR; kdefl >= 0: FGMRES-DR keeping kdefl harmonic Ritz vectors
 static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<int>& nrhs, void* const* x,
                             const void* const* b, const wc_solver_params* p, wc_solver_stats* st_out, void* stream,
-                            Batch* cached) {
+                            Batch* cached, int kdefl = -1) {
   int rc = WC_OK;
   int grc = guarded([&] {
     require(p, WC_ERR_ARG, "null params");
@@ -943,17 +1226,27 @@ static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<
       B = owned.get();
     }
     SolveSetup s = make_setup(*p, ctxs[0], max_nrhs);
-    prepare_solver(*B, s);
+    require(kdefl < s.nkv, WC_ERR_ARG, "FGMRES-DR needs fewer deflated vectors than the cycle length");
+    if (kdefl >= 0)
+      prepare_fgmres(*B, s);
+    else
+      prepare_solver(*B, s);
     pack_batch(*B, P_F64, b, B->b, st);
     if (p->x0_given) pack_batch(*B, P_F64, (const void* const*)x, B->x, st);
     std::vector<wc_solver_stats> stats;
-    rc = fgcr_solve(*B, s, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
+    if (kdefl >= 0)
+      rc = fgmres_dr_solve(*B, s, kdefl, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
+    else
+      rc = fgcr_solve(*B, s, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
     unpack_batch(*B, P_F64, B->x, x, -1, st);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(st));
     if (st_out)
       for (size_t i = 0; i < stats.size(); ++i) st_out[i] = stats[i];
-    if (rc != WC_OK) g_last_error = rc == WC_ERR_BREAKDOWN ? "FGCR breakdown" : "FGCR did not converge within maxit";
+    if (rc != WC_OK) {
+      const char* what = kdefl >= 0 ? "FGMRES-DR" : "FGCR";
+      g_last_error = std::string(what) + (rc == WC_ERR_BREAKDOWN ? " breakdown" : " did not converge within maxit");
+    }
   });
   return grc != WC_OK ? grc : rc;
 }
@@ -970,6 +1263,20 @@ int wc_fgcr_solve(wc_ctx* c, void* x, const void* b, int nrhs, const wc_solver_p
   void* xs[1] = {x};
   const void* bs[1] = {b};
   return solve_batch_impl({c}, {nrhs}, xs, bs, p, st, stream, B);
+}
+
+int wc_fgmres_dr_solve(wc_ctx* c, void* x, const void* b, int nrhs, const wc_solver_params* p, int kdefl,
+                       wc_solver_stats* st, void* stream) {
+  if (!c || nrhs < 1 || kdefl < 0) {
+    g_last_error = "null context, nrhs < 1 or kdefl < 0";
+    return WC_ERR_ARG;
+  }
+  Batch* B = nullptr;
+  int rc = guarded([&] { B = &ctx_batch(c, nrhs); });
+  if (rc != WC_OK) return rc;
+  void* xs[1] = {x};
+  const void* bs[1] = {b};
+  return solve_batch_impl({c}, {nrhs}, xs, bs, p, st, stream, B, kdefl);
 }
 
 int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,

@@ -92,6 +92,25 @@ struct SysState {
   double2 alpha[NKV_MAX];
 };
 
+// FGMRES-DR state per system: the cycle's (m+1) x m matrix Hbar, its Givens rotations and
+// rotated residual coefficients g (|g[j+1]| = least-squares residual after column j), and
+// the deflation basis P used to recombine V and Z at a restart.
+constexpr int ARN_LD = NKV_MAX + 1;
+constexpr int ARN_ROT_MAX = NKV_MAX * (NKV_MAX + 1) / 2 + NKV_MAX + 1;
+struct ArnState {
+  int nrot;      // rotations in use
+  int lucky;     // the last new basis vector was (numerically) zero: invariant subspace
+  int pin, pout; // P is pin x pout
+  double2 H[ARN_LD * NKV_MAX];  // column-major, leading dimension ARN_LD
+  double2 g[ARN_LD];
+  double rc[ARN_ROT_MAX];
+  double2 rs[ARN_ROT_MAX];
+  int rp[ARN_ROT_MAX];
+  double2 P[ARN_LD * ARN_LD];   // column-major, leading dimension ARN_LD
+  double2 h1[ARN_LD], h2[ARN_LD];  // the two Gram-Schmidt passes' coefficients of column j
+  double w2;                       // |w|^2 before the first pass
+};
+
 struct VecLaunch {
   const LatDesc* lats;
   const WorkItem* items;   // nr = 1
@@ -110,6 +129,7 @@ struct VecLaunch {
   double2* const* phi;
   // SAP-precision field for conversions
   void* sp; float* sp_sc;
+  ArnState* arn;           // FGMRES-DR state per system (null for FGCR)
 };
 // phi_k = |r| * psi(P)      (psi from the SAP) ; eta(P) = r / |r|
 void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
@@ -125,6 +145,22 @@ enum ReduceOp { RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INIT
 void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
                    hipStream_t st);
 void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st);
+
+// ----------------------------------------------------------------- FGMRES-DR (Arnoldi in FP64)
+// a.chi = basis V (m+1 entries), a.phi = preconditioned directions Z, a.k = column j
+void launch_arn_init(const VecLaunch& a, int grid, hipStream_t st);               // V_0 = r / |r|
+void launch_arn_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);   // eta(P) = V_j
+void launch_arn_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st); // Z_j = psi
+// Gram-Schmidt twice: dots (h1 = <V_i, w>), reduce pass 1, w -= sum h1_i V_i with the
+// second pass's dots fused (h2 = <V_i, w>, |w|^2), reduce pass 2 (column j of Hbar = h1 + h2,
+// h_{j+1,j}, Givens, stop test), then V_{j+1} = (w - sum h2_i V_i) / h_{j+1,j}
+void launch_arn_dots(const VecLaunch& a, int grid, hipStream_t st);
+void launch_arn_reduce(int pass, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks, int m,
+                       hipStream_t st);
+void launch_arn_update1(const VecLaunch& a, int grid, hipStream_t st);
+void launch_arn_update(const VecLaunch& a, int grid, hipStream_t st);
+// V_l <- sum_i P_il V_i (l < pout, i < pin), Z_l <- sum_i P_il Z_i (l < pout-1, i < pin-1), in place
+void launch_arn_recombine(const VecLaunch& a, int grid, hipStream_t st);
 
 // ----------------------------------------------------------------- force
 // K_mu(x) += coef * d Re<Y, D X>/dU (torch convention: G = K^dag) per link, canonical [4][V][3][3]
