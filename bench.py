@@ -12,7 +12,8 @@ the solve divided by the step time).  Beside it: the FP64 solve time on the same
 mixed solve with the unpreconditioned block solver, D_w GB/s and Gflop/s per storage
 precision against the 8 TB/s HBM roofline, the roofline record of the dominant kernel
 (the Schwarz block solver, bound by vector ALU), the batched 12-point-source solve on
-24^3 x 48 against 12 single FP64 solves, the 32^3 x 64 solve on 16-bit storage, and the
+24^3 x 48 against 12 single FP64 solves, the 32^3 x 64 solve on 16-bit storage, FGCR
+against FGMRES-DR close to the critical mass (the regime of the paper's Fig. 1), and the
 FP64 oracle timed on the host for a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -187,7 +188,39 @@ def extra_workloads(wc, torch, dev):
         rec[sp] = {"ms": t, "iters": st[0]["iters"], "true_rel_residual": st[0]["rel_true_res"],
                    "rel_err_vs_fp64_solution": rel}
     out["solve_32c64"] = rec
+    del lat, b
+    out["near_critical_16c32"] = near_critical(wc, torch, dev)
     return out
+
+
+def near_critical(wc, torch, dev):
+    """The regime of the paper's Fig. 1: m0 = -0.178, close to the critical mass of the
+    synthetic eps = 0.3 field on 16^3 x 32.  FGCR with restart 16 and 32 against
+    FGMRES-DR with 32 vectors of which 10 are deflated harmonic Ritz vectors; same FP32
+    even/odd SAP preconditioner, FP64 outer solver, tol 1e-10."""
+    import synth
+    m0 = -0.178
+    lat = wc.Lattice(torch.from_numpy(synth.gauge_field(DIMS)).to(dev), block=BLOCK, m0=m0, csw=CSW)
+    b = torch.from_numpy(synth.gaussian_spinor(DIMS)).to(dev)
+    rec = {"m0": m0}
+
+    def run(name, f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = f()
+        torch.cuda.synchronize()
+        rec[name] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": st[0]["iters"],
+                     "restarts": st[0]["restarts"], "true_rel_residual": st[0]["rel_true_res"],
+                     "status": st[0]["status"]}
+
+    kw = dict(ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f32", eo=1, maxit=3000)
+    run("fgcr_16", lambda: lat.solve(b, check=False, nkv=16, **kw))
+    run("fgcr_32", lambda: lat.solve(b, check=False, nkv=32, **kw))
+    run("fgmres_32", lambda: lat.solve_fgmres_dr(b, k=0, check=False, nkv=32, **kw))
+    run("fgmres_dr_32_10", lambda: lat.solve_fgmres_dr(b, k=10, check=False, nkv=32, **kw))
+    rec["speedup_dr_vs_fgcr_32"] = rec["fgcr_32"]["ms"] / rec["fgmres_dr_32_10"]["ms"]
+    return rec
 
 
 def summarise_pmc(fetch_csv, write_csv, out_json):
