@@ -200,7 +200,7 @@ __global__ __launch_bounds__(WG) void k_copy(VecLaunch a, double2* dst, const do
 // ------------------------------------------------------------------ per-system reductions
 
 __global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
-  __shared__ double lds[(WG / 64) * 4 * NKV_MAX];
+  __shared__ double lds[WG];
   const int sys = blockIdx.x;
   SysState& S = a.sys[sys];
   const int nv = op == RED_GS ? 4 * a.k + 3 : 1;
@@ -208,24 +208,9 @@ __global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* s
   if (!global_op && (a.skip[sys] != 0)) return;
   if ((op == RED_TRUE || op == RED_INITR) && S.converged) return;
   if (nv == 0) return;
-  double acc[4 * NKV_MAX];
-  for (int j = 0; j < nv; ++j) acc[j] = 0.0;
-  const int p0 = sys_part[sys], nc = sys_nchunks[sys];
-  for (int c = threadIdx.x; c < nc; c += WG)
-    for (int j = 0; j < nv; ++j) acc[j] += a.partials[(size_t)(p0 + c) * a.pw + j];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int j = 0; j < nv; ++j) {
-    double t = wave_sum(acc[j]);
-    if (lane == 0) lds[wid * 4 * NKV_MAX + j] = t;
-  }
-  __syncthreads();
+  sum_partials(a.partials, a.pw, sys_part[sys], sys_nchunks[sys], nv, lds);
   if (threadIdx.x != 0) return;
-  double sum[4 * NKV_MAX];
-  for (int j = 0; j < nv; ++j) {
-    double t = 0.0;
-    for (int w = 0; w < WG / 64; ++w) t += lds[w * 4 * NKV_MAX + j];
-    sum[j] = t;
-  }
+  const double* sum = lds;
   const int k = a.k;
   switch (op) {
     case RED_GS: {

@@ -177,32 +177,16 @@ __global__ __launch_bounds__(WG) void k_arn_update1(VecLaunch a) {
 // the tolerance, at maxit or on a breakdown.
 __global__ __launch_bounds__(WG) void k_arn_reduce(int pass, VecLaunch a, const int* sys_part, const int* sys_nchunks,
                                                    int m) {
-  constexpr int LD = 2 * ARN_LD + 2;
-  __shared__ double lds[(WG / 64) * LD];
+  __shared__ double lds[WG];
   const int sys = blockIdx.x;
   if (a.skip[sys]) return;
   SysState& S = a.sys[sys];
   ArnState& A = a.arn[sys];
   const int j = a.k;
   const int nv = 2 * (j + 1) + 1;
-  double acc[LD];
-  for (int i = 0; i < nv; ++i) acc[i] = 0.0;
-  const int p0 = sys_part[sys], nc = sys_nchunks[sys];
-  for (int c = threadIdx.x; c < nc; c += WG)
-    for (int i = 0; i < nv; ++i) acc[i] += a.partials[(size_t)(p0 + c) * a.pw + i];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = 0; i < nv; ++i) {
-    const double t = wave_sum(acc[i]);
-    if (lane == 0) lds[wid * LD + i] = t;
-  }
-  __syncthreads();
+  sum_partials(a.partials, a.pw, sys_part[sys], sys_nchunks[sys], nv, lds);
   if (threadIdx.x != 0) return;
-  double sum[LD];
-  for (int i = 0; i < nv; ++i) {
-    double t = 0.0;
-    for (int q = 0; q < WG / 64; ++q) t += lds[q * LD + i];
-    sum[i] = t;
-  }
+  const double* sum = lds;
   if (pass == 1) {
     for (int i = 0; i <= j; ++i) A.h1[i] = make_double2(sum[2 * i], sum[2 * i + 1]);
     A.w2 = sum[2 * (j + 1)];

@@ -46,4 +46,25 @@ template <int NV> WC_D void put_partial(const VecLaunch& a, const VecSite& v, do
   }
 }
 
+// Per-system sums of the first nv values of the nc chunk partials starting at p0
+// (nv <= pw).  The work-group splits into groups of nvp = next power of two >= nv lanes;
+// lane j of group g adds value j of chunks g, g + groups, ..., so consecutive lanes read
+// consecutive words, and the groups are then added by a fixed tree.  Every thread of the
+// work-group calls this (lds: WG doubles); afterwards lds[j] holds the sum of value j.
+WC_D void sum_partials(const double* partials, int pw, long long p0, int nc, int nv, double* lds) {
+  int nvp = 1;
+  while (nvp < nv) nvp <<= 1;
+  const int groups = WG / nvp;
+  const int t = threadIdx.x, j = t % nvp, grp = t / nvp;
+  double acc = 0.0;
+  if (j < nv)
+    for (int c = grp; c < nc; c += groups) acc += partials[(size_t)(p0 + c) * pw + j];
+  lds[t] = acc;
+  __syncthreads();
+  for (int step = groups >> 1; step > 0; step >>= 1) {
+    if (grp < step) lds[t] += lds[t + step * nvp];
+    __syncthreads();
+  }
+}
+
 }  // namespace wc
