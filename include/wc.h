@@ -156,6 +156,11 @@ int wc_fgmres_dr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_s
 int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
                         const wc_solver_params* p, wc_solver_stats* st, void* stream);
 
+/* FGMRES-DR (as wc_fgmres_dr_solve) for nlat lattices of different sizes solved together,
+ * arguments as wc_fgcr_solve_batch. */
+int wc_fgmres_dr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
+                             const wc_solver_params* p, int kdefl, wc_solver_stats* st, void* stream);
+
 /* G = coef * dL/dU for L = sum_r Re <Y_r, D X_r> in torch's complex-gradient convention
  * (dL = Re sum tr(G^dag dU)), complex128 [4][L0..L3][3][3].  Hopping and clover terms
  * (product rule over the plaquette leaves).  Used for the backward of D and of D^-1. */

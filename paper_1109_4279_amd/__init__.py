@@ -219,8 +219,9 @@ class Lattice:
         return ms.value
 
 
-def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, check=True, **kw):
-    """Solve several lattices (possibly of different sizes) in one batched solve.
+def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, check=True, k=None, **kw):
+    """Solve several lattices (possibly of different sizes) in one batched solve: FGCR, or
+    FGMRES-DR keeping k harmonic Ritz vectors when k is given.
 
     bs[i] is a complex128 [nrhs_i][dims_i][4][3] tensor.  Returns (xs, stats)."""
     lib = _lib.load()
@@ -236,7 +237,10 @@ def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, c
     bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
     nrhs = (ctypes.c_int * n)(*nr)
     st = (SolverStats * sum(nr))()
-    rc = lib.wc_fgcr_solve_batch(ctxs, n, xp, bp, nrhs, ctypes.byref(p), st, _stream(stream))
+    if k is None:
+        rc = lib.wc_fgcr_solve_batch(ctxs, n, xp, bp, nrhs, ctypes.byref(p), st, _stream(stream))
+    else:
+        rc = lib.wc_fgmres_dr_solve_batch(ctxs, n, xp, bp, nrhs, ctypes.byref(p), int(k), st, _stream(stream))
     if check:
         _lib.check(rc)
     return xs, [s.as_dict() for s in st]

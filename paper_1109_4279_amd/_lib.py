@@ -52,6 +52,9 @@ _SIGS = {
     "wc_clover_export": (_I, [_P, _P, _P]),
     "wc_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
     "wc_harmonic_ritz": (_I, [_I, _P, _P, _P]),
+    "wc_fgmres_dr_solve_batch": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                      ctypes.POINTER(_I), ctypes.POINTER(SolverParams), _I, ctypes.POINTER(SolverStats),
+                                      _P]),
     "wc_fgmres_dr_solve": (_I, [_P, _P, _P, _I, ctypes.POINTER(SolverParams), _I, ctypes.POINTER(SolverStats), _P]),
     "wc_sap_block_mr": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),
     "wc_sap": (_I, [_P, _P, _P, _I, _I, _I, _I, _I, _P]),

@@ -1290,6 +1290,17 @@ int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const voi
   return solve_batch_impl(cs, ns, x, b, p, st, stream, nullptr);
 }
 
+int wc_fgmres_dr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
+                             const wc_solver_params* p, int kdefl, wc_solver_stats* st, void* stream) {
+  if (!ctxs || nlat < 1 || !x || !b || !nrhs || kdefl < 0) {
+    g_last_error = "null argument or kdefl < 0";
+    return WC_ERR_ARG;
+  }
+  std::vector<wc_ctx*> cs(ctxs, ctxs + nlat);
+  std::vector<int> ns(nrhs, nrhs + nlat);
+  return solve_batch_impl(cs, ns, x, b, p, st, stream, nullptr, kdefl);
+}
+
 int wc_link_grad(wc_ctx* c, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream) {
   return guarded([&] {
     require(c && G && Y && X && nrhs >= 1, WC_ERR_ARG, "bad argument");

@@ -26,11 +26,14 @@ def test_dirac_apply_gradcheck():
     assert torch.autograd.gradcheck(f, (U, x), eps=1e-6, atol=1e-7, rtol=1e-6, fast_mode=True)
 
 
-def test_dirac_solve_gradcheck():
+@pytest.mark.parametrize("eo", [0, 1])
+def test_dirac_solve_gradcheck(eo):
+    """Through the solve with either block solver (single-site blocks: with even/odd the
+    block solve is the exact inverse of the site's clover term on both parities)."""
     from paper_1109_4279_amd.autograd import dirac_solve
     torch, U, b = _inputs(62)
     f = lambda U_, b_: dirac_solve(U_, b_, block=BLOCK, m0=0.2, csw=1.0, tol=1e-14, maxit=400,
-                                   sap_prec="f64", nkv=12)
+                                   sap_prec="f64", nkv=12, eo=eo)
     assert torch.autograd.gradcheck(f, (U, b), eps=1e-5, atol=1e-6, rtol=1e-5, fast_mode=True)
 
 

@@ -87,6 +87,26 @@ def test_fgmres_dr_deflation_helps_near_critical():
     assert s_dr[0]["iters"] < s_gcr[0]["iters"]
 
 
+def test_fgmres_dr_uneven_batch():
+    """Lattices of three sizes (one with 4x3x3x3 blocks) and several rhs each in one
+    FGMRES-DR solve."""
+    import paper_1109_4279_amd as wc
+    m0, csw = -0.1, 1.0
+    specs = [((16, 8, 8, 8), (4, 4, 4, 4)), ((24, 12, 12, 12), (4, 3, 3, 3)), ((8, 4, 4, 4), (2, 2, 2, 2))]
+    lats, bs = [], []
+    for i, (dims, block) in enumerate(specs):
+        lats.append(lattice(dims, block, m0, csw, seed=synth.GAUGE_SEED + i))
+        bs.append(synth.gaussian_spinor(dims, nrhs=2, seed=synth.RHS_SEED + i))
+    xs, st = wc.solve_batch(lats, [to_dev(b) for b in bs], tol=1e-10, sap_prec="f32", eo=1, nkv=8, k=3)
+    k = 0
+    for i, (dims, block) in enumerate(specs):
+        x = to_np(xs[i])
+        for r in range(2):
+            assert st[k]["status"] == 0
+            assert _true_res(dims, m0, csw, x[r], bs[i][r], seed=synth.GAUGE_SEED + i) <= 1e-10
+            k += 1
+
+
 def test_fgmres_dr_argument_errors():
     import paper_1109_4279_amd as wc
     dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
