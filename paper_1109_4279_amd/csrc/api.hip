@@ -447,8 +447,10 @@ static bool sap_colour_split(int prec, int nr) {
   return forced == 3 && prec != P_F64 && nr == 1;
 }
 
+// odd_rho: residual on odd sites for the even/odd solver (see SapLaunch::odd_rho)
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
-                              const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st) {
+                              const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st,
+                              int odd_rho = 0) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
   require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
@@ -474,6 +476,7 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.write_z = wz;
   a.cache = sap_cache_mode(it.n);
   a.uniform_bvol = B.uniform_bvol;
+  a.odd_rho = odd_rho;
   if (eo)
     launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), B.max_bvol, st);
   else if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
@@ -491,8 +494,10 @@ static void run_sap(Batch& B, int prec, int nr, int ncy, int nmr, Field& rho, Fi
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
       const bool last = (cy == ncy - 1);
+      // the SAP's residual field is private: odd sites are read from it only on the first
+      // visit of a block (later they hold the zero the previous solve left) and never stored
       run_sap_halfsweep(B, prec, nr, c, nmr, rho, z, psi, skip, cy == 0, !(cy == 0 && c == 0), !last,
-                        !(last && c == 1), eo, st);
+                        !(last && c == 1), eo, st, cy == 0 ? 1 : 2);
     }
 }
 
@@ -1423,7 +1428,8 @@ int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int eo, int iters, doub
     HIPCK(hipStreamSynchronize(st));
     int colour = 0;
     *ms = time_launches(c, st, iters, [&](hipStream_t s) {
-      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, eo, s);
+      // a half-sweep as the solver's later cycles run it (border update, odd residual implicit)
+      run_sap_halfsweep(B, prec, nr, colour, nmr, B.sap_rho, B.sap_z, B.sap_psi, nullptr, 0, 1, 1, 1, eo, s, 2);
       colour ^= 1;
     });
     HIPCK(hipGetLastError());

@@ -336,8 +336,14 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     cplx<R> re[NR][6], eo[NR][6];
     {
       Spinor<R> v[NR];
+      const bool implicit_zero = s == 1 && a.odd_rho == 2;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) v[r] = SpinorIO<P>::load(frho[r], own);
+      for (int r = 0; r < NR; ++r) {
+        if (implicit_zero)
+          zero(v[r]);
+        else
+          v[r] = SpinorIO<P>::load(frho[r], own);
+      }
       if (a.border && own_act) border_update<P, NR>(L, g, own, tile, tc, s ? lco : lce, fz, v);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
         RH.c[2 + i / 3][i % 3] = s ? zero_c : x;
       }
       if (!own_act || r >= w.nr || (a.skip && a.skip[L.sys0 + w.rhs0 + r])) continue;
-      if (a.write_rho) SpinorIO<P>::store(frho[r], own, RH);
+      if (a.write_rho && !(s == 1 && a.odd_rho != 0)) SpinorIO<P>::store(frho[r], own, RH);
       if (a.write_z) SpinorIO<P>::store(fz[r], own, Z);
       if (!a.first) {
         const Spinor<R> p = SpinorIO<P>::load(fpsi[r], own);

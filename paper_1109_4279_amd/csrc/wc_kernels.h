@@ -44,6 +44,9 @@ struct SapLaunch {
   int write_z;
   int cache;        // keep links and clover in registers across the MR steps (FP32 math only)
   int uniform_bvol; // block volume shared by every lattice of the launch (0 if they differ)
+  // even/odd solver, residual on odd sites (zero after every solve of the block):
+  // 0 read and stored, 1 read but not stored, 2 neither read (taken as zero) nor stored
+  int odd_rho;
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
