@@ -76,13 +76,17 @@ _SIGS = {
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libwc.so and declare every exported entry point; raises if it is missing."""
+def load(path: str | None = None):
+    """Load libwc.so (the in-tree build unless `path` is given) and declare every exported
+    entry point; raises if it is missing.  torch is imported first so that the library
+    binds to the HIP runtime torch already loaded: one runtime per process."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1109_4279_amd.build`")
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
