@@ -199,7 +199,8 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
         sums[3 * r + 1] = qr_im;
         sums[3 * r + 2] = qq;
       }
-      block_sum<3 * NR>(sums, red);
+      // the LDS exchange of this step put a barrier after the previous reduction's reads
+      block_sum<3 * NR, false>(sums, red);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double qq = sums[3 * r + 2];

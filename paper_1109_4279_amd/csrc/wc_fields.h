@@ -346,12 +346,13 @@ template <class T> WC_D T wave_sum(T v) {
 }
 
 // Sum over the work-group of up to N values per thread; result valid in every thread.
-// `lds` needs (blockDim/64) * N doubles.
-template <int N> WC_D void block_sum(double* v, double* lds) {
+// `lds` needs (blockDim/64) * N doubles.  GUARD = false drops the barrier that protects
+// `lds` from the previous call's readers, for callers that pass a barrier in between.
+template <int N, bool GUARD = true> WC_D void block_sum(double* v, double* lds) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
-  __syncthreads();
+  if (GUARD) __syncthreads();
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < N; ++i) lds[wid * N + i] = v[i];
