@@ -152,6 +152,7 @@ struct wc_ctx {
   bool have_clov_eo[4] = {false, false, false, false};
   wc::DevBuf tiles[2];
   wc::DevBuf eo_sites;                    // [corner parity][site parity][(bvol+1)/2] local indices
+  wc::DevBuf eo_slot;                     // [corner parity][bvol] parity-sorted slot of each local site
   int nr_dirac[4] = {0, 0, 0, 0};
   int nr_sap[4] = {0, 0, 0, 0};
   int nr_sap_eo[4] = {0, 0, 0, 0};
@@ -302,6 +303,7 @@ struct Batch {
       L.clov_eo = nullptr;
       L.cscale_eo = nullptr;
       L.eo_sites = c->eo_sites.as<short>();
+      L.eo_slot = c->eo_slot.as<short>();
       if (eo) {
         ensure_clover_eo(c, prec, st);
         L.clov_eo = c->clov_eo[prec].p;
@@ -1031,18 +1033,22 @@ static void layout(wc_ctx* c, const int* block, hipStream_t st) {
   HIPCK(hipMemcpy(c->tiles[1].p, t1.data(), sizeof(int) * t1.size(), hipMemcpyHostToDevice));
   // even and odd sites of a tile in local order, for both parities of the tile's corner
   const int nh = (c->g.bvol + 1) / 2;
-  std::vector<short> lut(4 * (size_t)nh, (short)-1);
+  // and each site's slot when the even sites come first, then the odd ones, in that order
+  std::vector<short> lut(4 * (size_t)nh, (short)-1), slot(2 * (size_t)c->g.bvol);
   for (int cp = 0; cp < 2; ++cp) {
     int cnt[2] = {0, 0};
     for (int l = 0; l < c->g.bvol; ++l) {
       int lc[4];
       local_coords(c->g, l, lc);
       const int par = (cp + lc[0] + lc[1] + lc[2] + lc[3]) & 1;
+      slot[(size_t)cp * c->g.bvol + l] = (short)(par * nh + cnt[par]);
       lut[(size_t)(2 * cp + par) * nh + cnt[par]++] = (short)l;
     }
   }
   c->eo_sites.ensure(sizeof(short) * lut.size());
   HIPCK(hipMemcpy(c->eo_sites.p, lut.data(), sizeof(short) * lut.size(), hipMemcpyHostToDevice));
+  c->eo_slot.ensure(sizeof(short) * slot.size());
+  HIPCK(hipMemcpy(c->eo_slot.p, slot.data(), sizeof(short) * slot.size(), hipMemcpyHostToDevice));
   for (int p = 0; p < 4; ++p) {
     c->have_links[p] = false;
     c->have_clov[p] = false;

@@ -22,7 +22,8 @@
 //    chirality block of the pair's hop sum;
 //  * with `cache` the eight links and two clover blocks a lane uses are loaded once per
 //    half-sweep and held in registers across the MR steps.
-// An application of S is two phases through one LDS buffer of the block: the even-site
+// An application of S is two phases through one LDS buffer of the block (rows of slots:
+// even sites first, then odd ones, each in pair order): the even-site
 // vector is written to the even slots, the odd sites form w_o = A_oo^-1 H_oe v into the
 // odd slots, then the even sites form A_ee v - H_eo w_o.  The set-up (residual update from
 // the other colour's latest block solutions) and the final stores are split by site
@@ -33,7 +34,15 @@ namespace wc {
 
 constexpr int EO_MAX_WAVES = 4;  // blocks of at most 256 sites: 128 pairs, 256 lanes
 
-template <class R> WC_D cplx<R> shfl1(cplx<R> v) { return {__shfl_xor(v.re, 1), __shfl_xor(v.im, 1)}; }
+// value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]: a VALU move,
+// no LDS round trip.  Every lane of the wavefront must execute it.
+WC_D float xor1(float v) { return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)); }
+WC_D double xor1(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <class R> WC_D cplx<R> shfl1(cplx<R> v) { return {xor1(v.re), xor1(v.im)}; }
 
 // acc += w * (1 + SGN gamma_mu)-hop of the transported neighbour spinor p, for mu = 2s + J.
 // J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.  sg = +1 for s = 0, -1 for s = 1.
@@ -93,13 +102,15 @@ template <class R, bool CACHE> struct LaneSite {
   int local;       // its index inside the tile
   int lnf[2];      // tile-local index of the forward / backward neighbour along mu = 2s + j
   int lnb[2];
+  int snf[2], snb[2];  // their LDS slots (even sites first, then odd, each in pair order)
   bool f[2], b[2]; // neighbour inside the block
   SU3<R> Uf[CACHE ? 2 : 1], Ub[CACHE ? 2 : 1];
   Herm6<R> C[CACHE ? 1 : 1];  // clover block s (scaled) when cached
 };
 
 template <int P, class R, bool CACHE>
-WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const int* lc, int s, LaneSite<R, CACHE>& x) {
+WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const int* lc, int s, const short* slot,
+                    LaneSite<R, CACHE>& x) {
   x.site = site;
   x.local = local;
 #pragma unroll
@@ -111,6 +122,8 @@ WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const 
     x.b[j] = m > 0;
     x.lnf[j] = local + (x.f[j] ? st : 0);
     x.lnb[j] = local - (x.b[j] ? st : 0);
+    x.snf[j] = slot[x.lnf[j]];
+    x.snb[j] = slot[x.lnb[j]];
   }
   if (CACHE) {
     const int base = site - local;
@@ -165,16 +178,16 @@ WC_D Herm6<R> clover_block_scaled(const LatDesc& L, int V, int site, int blk) {
 }
 
 template <int NR, class R>
-WC_D void lds_spinor(const cplx<R>* lds, int bvol, int r, int local, Spinor<R>& p) {
+WC_D void lds_spinor(const cplx<R>* lds, int ls, int r, int slot, Spinor<R>& p) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * bvol + local];
+  for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = lds[(r * 12 + k) * ls + slot];
 }
 
 // out[r] = chirality block s of wt * (sum of this pair's in-block hops at site x), read from
 // LDS.  Every lane of the wavefront must call this (it shuffles).
 template <int P, int NR, bool CACHE, class R>
 WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x, bool act, const cplx<R>* lds,
-                    int s, R sg, R wt, cplx<R> (*out)[6]) {
+                    int ls, int s, R sg, R wt, cplx<R> (*out)[6]) {
   Spinor<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) zero(acc[r]);
@@ -189,7 +202,7 @@ WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           Spinor<R> p;
-          lds_spinor<NR>(lds, g.bvol, r, x.lnf[J], p);
+          lds_spinor<NR>(lds, ls, r, x.snf[J], p);
           hop_dir<R, J, -1, false>(U, p, s, sg, w, acc[r]);
         }
       }
@@ -200,7 +213,7 @@ WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           Spinor<R> p;
-          lds_spinor<NR>(lds, g.bvol, r, x.lnb[J], p);
+          lds_spinor<NR>(lds, ls, r, x.snb[J], p);
           hop_dir<R, J, +1, true>(U, p, s, sg, w, acc[r]);
         }
       }
@@ -233,11 +246,11 @@ WC_D void clover_half(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>&
 }
 
 template <int NR, class R>
-WC_D void half_to_lds(cplx<R>* lds, int bvol, int local, int s, const cplx<R> (*v)[6]) {
+WC_D void half_to_lds(cplx<R>* lds, int ls, int slot, int s, const cplx<R> (*v)[6]) {
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) lds[(r * 12 + 6 * s + i) * bvol + local] = v[r][i];
+    for (int i = 0; i < 6; ++i) lds[(r * 12 + 6 * s + i) * ls + slot] = v[r][i];
 }
 
 // rho(site) -= (D z)(site) for the hops from site into neighbouring blocks (the other
@@ -310,8 +323,10 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     local_coords(g, lel, lce);
     local_coords(g, lol, lco);
     LaneSite<R, CACHE> xe, xo;
-    lane_site<P, R, CACHE>(L, g, base + lel, lel, lce, s, xe);
-    lane_site<P, R, CACHE>(L, g, base + lol, lol, lco, s, xo);
+    const short* slot = L.eo_slot + cp * g.bvol;
+    const int ls = 2 * nh;  // LDS row: slots 0..nh-1 even sites, nh..2nh-1 odd sites, in pair order
+    lane_site<P, R, CACHE>(L, g, base + lel, lel, lce, s, slot, xe);
+    lane_site<P, R, CACHE>(L, g, base + lol, lol, lco, s, slot, xo);
     if (CACHE) {
       xe.C[0] = clover_block_scaled<P, R>(L, g.V, xe.site, s);
       xo.C[0] = clover_block_scaled<P, R>(L, g.V, xo.site, s);
@@ -361,11 +376,11 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     // t_o = A_oo^-1 eta_o ; source of the Schur system: eta_e - H_eo t_o
     cplx<R> to[NR][6];
     clover_half<P, NR, CACHE, false>(L, g, xo, s, eo, to);
-    if (ho) half_to_lds<NR>(lds, g.bvol, lo, s, to);
+    if (ho) half_to_lds<NR>(lds, ls, nh + pr, s, to);
     __syncthreads();
     {
       cplx<R> d[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, s, sg, R(0.5), d);
+      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, sg, R(0.5), d);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -379,17 +394,17 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
       for (int i = 0; i < 6; ++i) ze[r][i] = {R(0), R(0)};
     for (int it = 0; it < a.nmr; ++it) {
       // q = S rho_e = A_ee rho_e - H_eo A_oo^-1 H_oe rho_e   (H = -1/2 sum of hops)
-      if (he) half_to_lds<NR>(lds, g.bvol, le, s, re);
+      if (he) half_to_lds<NR>(lds, ls, pr, s, re);
       __syncthreads();
       {
         cplx<R> t[NR][6], wo[NR][6];
-        pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, s, sg, R(-0.5), t);
+        pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, sg, R(-0.5), t);
         clover_half<P, NR, CACHE, false>(L, g, xo, s, t, wo);
-        if (ho) half_to_lds<NR>(lds, g.bvol, lo, s, wo);
+        if (ho) half_to_lds<NR>(lds, ls, nh + pr, s, wo);
       }
       __syncthreads();
       cplx<R> q[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, s, sg, R(0.5), q);
+      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, sg, R(0.5), q);
       clover_half<P, NR, CACHE, true>(L, g, xe, s, re, q);
       double sums[3 * NR];
 #pragma unroll
@@ -425,12 +440,12 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     }
 
     // z_o = t_o - A_oo^-1 H_oe z_e
-    if (he) half_to_lds<NR>(lds, g.bvol, le, s, ze);
+    if (he) half_to_lds<NR>(lds, ls, pr, s, ze);
     __syncthreads();
     cplx<R> zo[NR][6];
     {
       cplx<R> t[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, s, sg, R(0.5), t);
+      pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, sg, R(0.5), t);
       clover_half<P, NR, CACHE, false>(L, g, xo, s, t, zo);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -473,7 +488,7 @@ static int eo_threads(int max_bvol) { return (2 * ((max_bvol + 1) / 2) + 63) / 6
 
 size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol) {
   const size_t cb = prec == P_F64 ? 16 : 8;
-  return sizeof(double) * EO_MAX_WAVES * 3 * nr + cb * 12 * (size_t)nr * max_bvol;
+  return sizeof(double) * EO_MAX_WAVES * 3 * nr + cb * 12 * (size_t)nr * (2 * ((max_bvol + 1) / 2));
 }
 
 template <int P>

@@ -26,6 +26,7 @@ struct LatDesc {
   const void* clov_eo;    // A on even sites, A^-1 on odd sites, storage precision of the launch
   const float* cscale_eo; // its 16-bit scales [V][2]
   const short* eo_sites;  // [corner parity][site parity][(bvol+1)/2] tile-local site indices, -1 = none
+  const short* eo_slot;   // [corner parity][bvol] slot of each tile-local site in the parity-sorted order
 };
 
 // A unit of work: WG consecutive sites (or one tile for the Schwarz kernels)
