@@ -310,7 +310,7 @@ __global__ __launch_bounds__(WG) void k_arn_recombine(VecLaunch a, int which) {
         const size_t e = base + (size_t)k * v.V + v.s;
         double2 in[NMAX];
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) in[i] = i < nin ? tab[i][e] : make_double2(0.0, 0.0);
+        for (int i = 0; i < NMAX; ++i) in[i] = i < nin ? gld_d2(tab[i], e) : make_double2(0.0, 0.0);
         for (int l = 0; l < nout; ++l) {
           double re = 0.0, im = 0.0;
 #pragma unroll

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
       for (int r = 0; r < w.nr; ++r) any |= (a.skip[L.sys0 + w.rhs0 + r] == 0);
     }
     if (!any) continue;
-    const int tile = L.tiles[a.colour][w.chunk];
+    const int tile = gld_i32(L.tiles[a.colour], w.chunk);
     const int t = threadIdx.x;
     const bool active = t < g.bvol;
     const int s = tile * g.bvol + (active ? t : 0);

@@ -1,4 +1,4 @@
-// Schwarz block MR with one lane per (site, colour): the production block solver.
+// Schwarz block MR with one lane per (site, colour): an opt-in variant of k_sap_mr.
 //
 // Same arithmetic as k_sap_mr (arXiv:1109.4279, Sec. 4: MR steps on the Dirichlet block
 // operator of every block of one chessboard colour, after the residual update from the
@@ -25,19 +25,19 @@ template <int P> struct Comp;
 template <> struct Comp<P_F64> {
   typedef double R;
   static WC_D cplx<R> spin(const FieldRef& f, int s, int c) {
-    double2 v = ((const double2*)f.d)[(size_t)c * f.V + s];
+    double2 v = gld_d2(f.d, (size_t)c * f.V + s);
     return {v.x, v.y};
   }
   static WC_D void spin_store(const FieldRef& f, int s, int c, cplx<R> v, float) {
     ((double2*)f.d)[(size_t)c * f.V + s] = make_double2(v.re, v.im);
   }
   static WC_D cplx<R> link(const void* g, const float*, int V, int mu, int s, int k) {
-    double2 v = ((const double2*)g)[((size_t)mu * 9 + k) * V + s];
+    double2 v = gld_d2(g, ((size_t)mu * 9 + k) * V + s);
     return {v.x, v.y};
   }
   static WC_D R clov(const void* c, const float*, int V, int s, int blk, int r) {
     const int g = 36 * blk + r;
-    const double2 v = ((const double2*)c)[(size_t)(g >> 1) * V + s];
+    const double2 v = gld_d2(c, (size_t)(g >> 1) * V + s);
     return (g & 1) ? v.y : v.x;
   }
 };
@@ -45,27 +45,27 @@ template <> struct Comp<P_F64> {
 template <> struct Comp<P_F32> {
   typedef float R;
   static WC_D cplx<R> spin(const FieldRef& f, int s, int c) {
-    float2 v = ((const float2*)f.d)[((size_t)(c >> 1) * f.V + s) * 2 + (c & 1)];
+    float2 v = gld_f2(f.d, ((size_t)(c >> 1) * f.V + s) * 2 + (c & 1));
     return {v.x, v.y};
   }
   static WC_D void spin_store(const FieldRef& f, int s, int c, cplx<R> v, float) {
     ((float2*)f.d)[((size_t)(c >> 1) * f.V + s) * 2 + (c & 1)] = make_float2(v.re, v.im);
   }
   static WC_D cplx<R> link(const void* g, const float*, int V, int mu, int s, int k) {
-    float2 v = ((const float2*)g)[((size_t)mu * 9 + k) * V + s];
+    float2 v = gld_f2(g, ((size_t)mu * 9 + k) * V + s);
     return {v.x, v.y};
   }
   static WC_D R clov(const void* c, const float*, int V, int s, int blk, int r) {
     const int g = 36 * blk + r;
-    return ((const float*)c)[((size_t)(g >> 2) * V + s) * 4 + (g & 3)];
+    return gld_f(c, ((size_t)(g >> 2) * V + s) * 4 + (g & 3));
   }
 };
 
 template <int P> struct Comp16 {
   typedef float R;
   static WC_D cplx<R> spin(const FieldRef& f, int s, int c) {
-    const uint32_t w = ((const uint32_t*)f.d)[((size_t)(c >> 2) * f.V + s) * 4 + (c & 3)];
-    const float sc = f.sc[s];
+    const uint32_t w = gld_u32(f.d, ((size_t)(c >> 2) * f.V + s) * 4 + (c & 3));
+    const float sc = gld_f(f.sc, s);
     return {sc * s16_to_f32<P>(uint16_t(w & 0xFFFFu)), sc * s16_to_f32<P>(uint16_t(w >> 16))};
   }
   // stores one component with the site scale `sc` agreed by the site's three lanes
@@ -77,17 +77,17 @@ template <int P> struct Comp16 {
   static WC_D cplx<R> link(const void* g, const float* sc, int V, int mu, int s, int k) {
     uint32_t w;
     if (k < 8)
-      w = ((const uint32_t*)g)[(((size_t)mu * 2 + (k >> 2)) * V + s) * 4 + (k & 3)];
+      w = gld_u32(g, (((size_t)mu * 2 + (k >> 2)) * V + s) * 4 + (k & 3));
     else
-      w = ((const uint32_t*)((const uint4*)g + (size_t)8 * V))[(size_t)mu * V + s];
-    const float f = sc[s];
+      w = gld_u32(g, (size_t)8 * V * 4 + (size_t)mu * V + s);
+    const float f = gld_f(sc, s);
     return {f * s16_to_f32<P>(uint16_t(w & 0xFFFFu)), f * s16_to_f32<P>(uint16_t(w >> 16))};
   }
   static WC_D R clov(const void* c, const float* sc, int V, int s, int blk, int r) {
     const int g = 36 * blk + r;
-    const uint32_t w = ((const uint32_t*)c)[((size_t)(g >> 3) * V + s) * 4 + ((g & 7) >> 1)];
+    const uint32_t w = gld_u32(c, ((size_t)(g >> 3) * V + s) * 4 + ((g & 7) >> 1));
     const uint16_t h = (g & 1) ? uint16_t(w >> 16) : uint16_t(w & 0xFFFFu);
-    return sc[2 * s + blk] * s16_to_f32<P>(h);
+    return gld_f(sc, 2 * (size_t)s + blk) * s16_to_f32<P>(h);
   }
 };
 template <> struct Comp<P_F16> : Comp16<P_F16> {};
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(768) void k_sap_mr3(SapLaunch a) {
     if (a.skip && a.skip[L.sys0 + w.rhs0]) continue;
     const int bvol = BV > 0 ? BV : g.bvol;
     float* cl = (float*)(lds + 12 * bvol);  // clover reals [72][bvol]
-    const int tile = L.tiles[a.colour][w.chunk];
+    const int tile = gld_i32(L.tiles[a.colour], w.chunk);
     const int tid = threadIdx.x;
     const bool active = tid < 3 * bvol;
     const int col = active ? tid / bvol : 0;   // colour component of this lane

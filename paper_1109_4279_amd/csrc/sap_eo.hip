@@ -28,21 +28,11 @@
 // odd slots, then the even sites form A_ee v - H_eo w_o.  The set-up (residual update from
 // the other colour's latest block solutions) and the final stores are split by site
 // instead: lane 0 works on the even site, lane 1 on the odd one.
-#include "wc_kernels.h"
+#include "sap_eo.h"
 
 namespace wc {
 
 constexpr int EO_MAX_WAVES = 4;  // blocks of at most 256 sites: 128 pairs, 256 lanes
-
-// value of the partner lane (lane ^ 1) by a DPP quad permutation [1, 0, 3, 2]: a VALU move,
-// no LDS round trip.  Every lane of the wavefront must execute it.
-WC_D float xor1(float v) { return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)); }
-WC_D double xor1(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <class R> WC_D cplx<R> shfl1(cplx<R> v) { return {xor1(v.re), xor1(v.im)}; }
 
 // acc += w * (1 + SGN gamma_mu)-hop of the transported neighbour spinor p, for mu = 2s + J.
 // J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.  sg = +1 for s = 0, -1 for s = 1.
@@ -122,8 +112,8 @@ WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const 
     x.b[j] = m > 0;
     x.lnf[j] = local + (x.f[j] ? st : 0);
     x.lnb[j] = local - (x.b[j] ? st : 0);
-    x.snf[j] = slot[x.lnf[j]];
-    x.snb[j] = slot[x.lnb[j]];
+    x.snf[j] = gld_s16(slot, x.lnf[j]);
+    x.snb[j] = gld_s16(slot, x.lnb[j]);
   }
   if (CACHE) {
     const int base = site - local;
@@ -133,48 +123,6 @@ WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const 
       x.Ub[CACHE ? j : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, 2 * s + j, base + x.lnb[j]);
     }
   }
-}
-
-// clover block blk (runtime) of the even/odd clover field, scale not applied
-template <int P, class R>
-WC_D Herm6<R> clover_block(const LatDesc& L, int V, int site, int blk) {
-  if constexpr (P == P_F64 || P == P_F32) {
-    return CloverIO<P>::load_raw(L.clov_eo, L.cscale_eo, V, site, blk);
-  } else {
-    // 72 halves per site in 9 uint4; block 0 is halves 0..35 of uint4 0..4, block 1 is
-    // halves 4..39 of uint4 4..8: load five uint4 from 4*blk and pick with a select
-    const uint4* p = (const uint4*)L.clov_eo + site + (size_t)(4 * blk) * V;
-    float H[40];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      uint4 v = p[(size_t)k * V];
-      uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        H[8 * k + 2 * j] = s16_to_f32<P>(uint16_t(w[j] & 0xFFFFu));
-        H[8 * k + 2 * j + 1] = s16_to_f32<P>(uint16_t(w[j] >> 16));
-      }
-    }
-    Herm6<R> h;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) h.d[i] = blk ? H[i + 4] : H[i];
-#pragma unroll
-    for (int k = 0; k < 15; ++k) h.o[k] = {blk ? H[10 + 2 * k] : H[6 + 2 * k], blk ? H[11 + 2 * k] : H[7 + 2 * k]};
-    return h;
-  }
-}
-
-template <int P, class R>
-WC_D Herm6<R> clover_block_scaled(const LatDesc& L, int V, int site, int blk) {
-  Herm6<R> h = clover_block<P, R>(L, V, site, blk);
-  const R cs = CloverIO<P>::scale(L.cscale_eo, site, blk);
-  if (P == P_F16 || P == P_BF16) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) h.d[i] *= cs;
-#pragma unroll
-    for (int k = 0; k < 15; ++k) h.o[k] = cs * h.o[k];
-  }
-  return h;
 }
 
 template <int NR, class R>
@@ -309,14 +257,14 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
       for (int r = 0; r < w.nr; ++r) any |= (a.skip[L.sys0 + w.rhs0 + r] == 0);
     }
     if (!any) continue;
-    const int tile = L.tiles[a.colour][w.chunk];
+    const int tile = gld_i32(L.tiles[a.colour], w.chunk);
     const int base = tile * g.bvol;
     const int nh = (g.bvol + 1) >> 1;
     int tc[4];
     tile_coords(g, tile, tc);
     const int cp = (tc[0] * g.B[0] + tc[1] * g.B[1] + tc[2] * g.B[2] + tc[3] * g.B[3]) & 1;
-    const int le = pr < nh ? L.eo_sites[(2 * cp) * nh + pr] : -1;
-    const int lo = pr < nh ? L.eo_sites[(2 * cp + 1) * nh + pr] : -1;
+    const int le = pr < nh ? gld_s16(L.eo_sites, (2 * cp) * nh + pr) : -1;
+    const int lo = pr < nh ? gld_s16(L.eo_sites, (2 * cp + 1) * nh + pr) : -1;
     const bool he = le >= 0, ho = lo >= 0;
     const int lel = he ? le : 0, lol = ho ? lo : 0;
     int lce[4], lco[4];

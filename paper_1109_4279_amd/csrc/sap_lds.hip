@@ -34,7 +34,7 @@ __global__ __launch_bounds__(NR * 256) void k_sap_mr_lds(SapLaunch a) {
     bool any = false;
     for (int r = 0; r < w.nr; ++r) any |= !(a.skip && a.skip[L.sys0 + w.rhs0 + r]);
     if (!any) continue;
-    const int tile = L.tiles[a.colour][w.chunk];
+    const int tile = gld_i32(L.tiles[a.colour], w.chunk);
     const int tid = threadIdx.x;
     const int rr = tid >> 8;         // rhs of this lane within the group
     const int l = tid & 255;         // site of this lane within the block
@@ -46,23 +46,21 @@ __global__ __launch_bounds__(NR * 256) void k_sap_mr_lds(SapLaunch a) {
 
     // stage the block operator (16-bit words as stored)
     {
-      const uint32_t* gl = (const uint32_t*)L.gauge;
       const int V = g.V;
       for (int j = rr; j < 36; j += NR) {
         const int mu = j / 9, k = j % 9;
         uint32_t v;
         if (k < 8)
-          v = gl[(((size_t)mu * 2 + (k >> 2)) * V + s) * 4 + (k & 3)];
+          v = gld_u32(L.gauge, (((size_t)mu * 2 + (k >> 2)) * V + s) * 4 + (k & 3));
         else
-          v = ((const uint32_t*)((const uint4*)L.gauge + (size_t)8 * V))[(size_t)mu * V + s];
+          v = gld_u32(L.gauge, (size_t)8 * V * 4 + (size_t)mu * V + s);
         lk[j * SL_BV + l] = v;
       }
-      const uint32_t* gc = (const uint32_t*)L.clov;
-      for (int j = rr; j < 36; j += NR) cw[j * SL_BV + l] = gc[((size_t)(j >> 2) * V + s) * 4 + (j & 3)];
+      for (int j = rr; j < 36; j += NR) cw[j * SL_BV + l] = gld_u32(L.clov, ((size_t)(j >> 2) * V + s) * 4 + (j & 3));
       if (rr == 0) {
-        lsc[l] = L.gscale[s];
-        csc[l] = L.cscale[2 * s];
-        csc[SL_BV + l] = L.cscale[2 * s + 1];
+        lsc[l] = gld_f(L.gscale, s);
+        csc[l] = gld_f(L.cscale, 2 * (size_t)s);
+        csc[SL_BV + l] = gld_f(L.cscale, 2 * (size_t)s + 1);
       }
     }
     __syncthreads();

@@ -46,6 +46,39 @@ WC_D int xcd_remap(int it, int n) {
   return (it & 7) * (n >> 3) + (it >> 3);
 }
 
+// ------------------------------------------------------------------ global loads
+
+// The operator fields are reached through pointers read from the LatDesc array in device
+// memory, which the compiler cannot prove to be global; loads through them would be flat
+// loads, and a flat load also counts against the wait counter of LDS and scalar loads, so
+// every LDS wait would drain the operator loads in flight.  These helpers load through
+// address-space-1 pointers (global_load).
+template <class T> using gptr_t = const __attribute__((address_space(1))) T*;
+typedef float gf2v __attribute__((ext_vector_type(2)));
+typedef float gf4v __attribute__((ext_vector_type(4)));
+typedef double gd2v __attribute__((ext_vector_type(2)));
+typedef unsigned gu4v __attribute__((ext_vector_type(4)));
+WC_D float2 gld_f2(const void* p, size_t i) {
+  const gf2v v = ((gptr_t<gf2v>)p)[i];
+  return make_float2(v.x, v.y);
+}
+WC_D float4 gld_f4(const void* p, size_t i) {
+  const gf4v v = ((gptr_t<gf4v>)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+WC_D double2 gld_d2(const void* p, size_t i) {
+  const gd2v v = ((gptr_t<gd2v>)p)[i];
+  return make_double2(v.x, v.y);
+}
+WC_D uint4 gld_u4(const void* p, size_t i) {
+  const gu4v v = ((gptr_t<gu4v>)p)[i];
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+WC_D uint32_t gld_u32(const void* p, size_t i) { return ((gptr_t<uint32_t>)p)[i]; }
+WC_D int gld_i32(const void* p, size_t i) { return ((gptr_t<int>)p)[i]; }
+WC_D short gld_s16(const void* p, size_t i) { return ((gptr_t<short>)p)[i]; }
+WC_D float gld_f(const void* p, size_t i) { return ((gptr_t<float>)p)[i]; }
+
 // ------------------------------------------------------------------ spinors
 
 // A spinor field view for one right-hand side: data + (16-bit) scales.
@@ -60,11 +93,10 @@ template <int P> struct SpinorIO;
 template <> struct SpinorIO<P_F64> {
   typedef double R;
   static WC_D Spinor<double> load(const FieldRef& f, int s) {
-    const double2* p = (const double2*)f.d + s;
     Spinor<double> o;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      double2 v = p[(size_t)k * f.V];
+      double2 v = gld_d2(f.d, (size_t)k * f.V + s);
       o.c[k / 3][k % 3] = {v.x, v.y};
     }
     return o;
@@ -82,11 +114,10 @@ template <> struct SpinorIO<P_F64> {
 template <> struct SpinorIO<P_F32> {
   typedef float R;
   static WC_D Spinor<float> load(const FieldRef& f, int s) {
-    const float4* p = (const float4*)f.d + s;
     Spinor<float> o;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float4 v = p[(size_t)k * f.V];
+      float4 v = gld_f4(f.d, (size_t)k * f.V + s);
       int c0 = 2 * k, c1 = 2 * k + 1;
       o.c[c0 / 3][c0 % 3] = {v.x, v.y};
       o.c[c1 / 3][c1 % 3] = {v.z, v.w};
@@ -111,11 +142,10 @@ template <int P> struct SpinorIO16 {
   typedef float R;
   // values without the site scale (multiply by scale() to get the field)
   static WC_D Spinor<float> load_raw(const FieldRef& f, int s) {
-    const uint4* p = (const uint4*)f.d + s;
     Spinor<float> o;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 v = p[(size_t)k * f.V];
+      uint4 v = gld_u4(f.d, (size_t)k * f.V + s);
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -125,14 +155,13 @@ template <int P> struct SpinorIO16 {
     }
     return o;
   }
-  static WC_D float scale(const FieldRef& f, int s) { return f.sc[s]; }
+  static WC_D float scale(const FieldRef& f, int s) { return gld_f(f.sc, s); }
   static WC_D Spinor<float> load(const FieldRef& f, int s) {
-    const uint4* p = (const uint4*)f.d + s;
-    float sc = f.sc[s];
+    float sc = gld_f(f.sc, s);
     Spinor<float> o;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint4 v = p[(size_t)k * f.V];
+      uint4 v = gld_u4(f.d, (size_t)k * f.V + s);
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -180,11 +209,11 @@ template <> struct LinkIO<P_F64> {
   static WC_D double scale(const float*, int) { return 1.0; }
   static WC_D SU3<double> load_raw(const void* g, const float* sc, int V, int mu, int s) { return load(g, sc, V, mu, s); }
   static WC_D SU3<double> load(const void* g, const float*, int V, int mu, int s) {
-    const double2* p = (const double2*)g + (size_t)mu * 9 * V + s;
+    const size_t p = (size_t)mu * 9 * V + s;
     SU3<double> u;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      double2 v = p[(size_t)k * V];
+      double2 v = gld_d2(g, p + (size_t)k * V);
       u.m[k / 3][k % 3] = {v.x, v.y};
     }
     return u;
@@ -194,24 +223,25 @@ template <> struct LinkIO<P_F32> {
   static WC_D float scale(const float*, int) { return 1.f; }
   static WC_D SU3<float> load_raw(const void* g, const float* sc, int V, int mu, int s) { return load(g, sc, V, mu, s); }
   static WC_D SU3<float> load(const void* g, const float*, int V, int mu, int s) {
-    const float2* p = (const float2*)g + (size_t)mu * 9 * V + s;
+    const size_t p = (size_t)mu * 9 * V + s;
     SU3<float> u;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float2 v = p[(size_t)k * V];
+      float2 v = gld_f2(g, p + (size_t)k * V);
       u.m[k / 3][k % 3] = {v.x, v.y};
     }
     return u;
   }
 };
 template <int P> struct LinkIO16 {
-  static WC_D float scale(const float* sc, int s) { return sc[s]; }
-  // link without the site scale
+  static WC_D float scale(const float* sc, int s) { return gld_f(sc, s); }
+  // link without the site scale: 8 words in uint4 arrays 2 mu, 2 mu + 1, the ninth in the
+  // word array after the eight uint4 arrays
   static WC_D SU3<float> load_raw(const void* g, const float*, int V, int mu, int s) {
-    const uint4* p = (const uint4*)g + (size_t)mu * 2 * V + s;
-    const uint32_t* q = (const uint32_t*)((const uint4*)g + (size_t)8 * V) + (size_t)mu * V + s;
-    uint4 a = p[0], b = p[V];
-    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, *q};
+    const size_t p = (size_t)mu * 2 * V + s;
+    const size_t q = (size_t)8 * V * 4 + (size_t)mu * V + s;
+    uint4 a = gld_u4(g, p), b = gld_u4(g, p + V);
+    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, gld_u32(g, q)};
     SU3<float> u;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
@@ -219,11 +249,11 @@ template <int P> struct LinkIO16 {
     return u;
   }
   static WC_D SU3<float> load(const void* g, const float* sc, int V, int mu, int s) {
-    const uint4* p = (const uint4*)g + (size_t)mu * 2 * V + s;
-    const uint32_t* q = (const uint32_t*)((const uint4*)g + (size_t)8 * V) + (size_t)mu * V + s;
-    float f = sc[s];
-    uint4 a = p[0], b = p[V];
-    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, *q};
+    const size_t p = (size_t)mu * 2 * V + s;
+    const size_t q = (size_t)8 * V * 4 + (size_t)mu * V + s;
+    float f = gld_f(sc, s);
+    uint4 a = gld_u4(g, p), b = gld_u4(g, p + V);
+    uint32_t w[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, gld_u32(g, q)};
     SU3<float> u;
 #pragma unroll
     for (int k = 0; k < 9; ++k)
@@ -250,17 +280,17 @@ template <> struct CloverIO<P_F64> {
   static WC_D double scale(const float*, int, int) { return 1.0; }
   static WC_D Herm6<double> load_raw(const void* c, const float* sc, int V, int s, int blk) { return load(c, sc, V, s, blk); }
   static WC_D Herm6<double> load(const void* c, const float*, int V, int s, int blk) {
-    const double2* p = (const double2*)c + (size_t)(18 * blk) * V + s;
+    const size_t p = (size_t)(18 * blk) * V + s;
     Herm6<double> h;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      double2 v = p[(size_t)k * V];
+      double2 v = gld_d2(c, p + (size_t)k * V);
       h.d[2 * k] = v.x;
       h.d[2 * k + 1] = v.y;
     }
 #pragma unroll
     for (int k = 0; k < 15; ++k) {
-      double2 v = p[(size_t)(3 + k) * V];
+      double2 v = gld_d2(c, p + (size_t)(3 + k) * V);
       h.o[k] = {v.x, v.y};
     }
     return h;
@@ -270,11 +300,11 @@ template <> struct CloverIO<P_F32> {
   static WC_D float scale(const float*, int, int) { return 1.f; }
   static WC_D Herm6<float> load_raw(const void* c, const float* sc, int V, int s, int blk) { return load(c, sc, V, s, blk); }
   static WC_D Herm6<float> load(const void* c, const float*, int V, int s, int blk) {
-    const float4* p = (const float4*)c + (size_t)(9 * blk) * V + s;
+    const size_t p = (size_t)(9 * blk) * V + s;
     float r[36];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      float4 v = p[(size_t)k * V];
+      float4 v = gld_f4(c, p + (size_t)k * V);
       r[4 * k] = v.x; r[4 * k + 1] = v.y; r[4 * k + 2] = v.z; r[4 * k + 3] = v.w;
     }
     Herm6<float> h;
@@ -286,23 +316,22 @@ template <> struct CloverIO<P_F32> {
   }
 };
 template <int P> struct CloverIO16 {
-  static WC_D float scale(const float* sc, int s, int blk) { return sc[2 * s + blk]; }
+  static WC_D float scale(const float* sc, int s, int blk) { return gld_f(sc, 2 * (size_t)s + blk); }
   static WC_D Herm6<float> load_raw(const void* c, const float*, int V, int s, int blk) {
     return load_impl(c, 1.f, V, s, blk);
   }
   static WC_D Herm6<float> load(const void* c, const float* sc, int V, int s, int blk) {
-    return load_impl(c, sc[2 * s + blk], V, s, blk);
+    return load_impl(c, scale(sc, s, blk), V, s, blk);
   }
   // 72 halves per site in 9 uint4; reals 36*blk .. 36*blk+35 belong to block blk
   static WC_D Herm6<float> load_impl(const void* c, float f, int V, int s, int blk) {
-    const uint4* p = (const uint4*)c + s;
     float r[36];
     // block 0 uses uint4 0..4 (reals 0..39), block 1 uses uint4 4..8 (reals 32..71)
     const int k0 = blk == 0 ? 0 : 4;
     const int off = blk == 0 ? 0 : 4;  // reals to skip at the start of uint4 k0
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      uint4 v = p[(size_t)(k0 + k) * V];
+      uint4 v = gld_u4(c, (size_t)(k0 + k) * V + s);
       uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
