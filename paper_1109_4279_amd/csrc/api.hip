@@ -223,7 +223,7 @@ struct Batch {
   std::map<int, ItemList> sap_items[2];     // by RHS tile
   DevBuf sys_part, sys_nchunks;
   DevBuf partials;
-  int pw = 4 * NKV_MAX;  // partial-sum width (at most WG: sum_partials)
+  int pw = 4 * NKV_MAX;  // partial-sum width (at most RWG: sum_partials)
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
   DevBuf d_chi, d_phi;

@@ -199,8 +199,8 @@ __global__ __launch_bounds__(WG) void k_copy(VecLaunch a, double2* dst, const do
 
 // ------------------------------------------------------------------ per-system reductions
 
-__global__ __launch_bounds__(WG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
-  __shared__ double lds[WG];
+__global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
+  __shared__ double lds[RWG];
   const int sys = blockIdx.x;
   SysState& S = a.sys[sys];
   const int nv = op == RED_GS ? 4 * a.k + 3 : 1;
@@ -330,7 +330,7 @@ void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int g
 }
 void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(WG), 0, st, op, a, sys_part, sys_nchunks);
+  hipLaunchKernelGGL(k_reduce, dim3(nsys), dim3(RWG), 0, st, op, a, sys_part, sys_nchunks);
 }
 void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st) {
   hipLaunchKernelGGL(k_backsub, dim3((nsys + 63) / 64), dim3(64), 0, st, a, nsys);

@@ -175,9 +175,9 @@ __global__ __launch_bounds__(WG) void k_arn_update1(VecLaunch a) {
 // orthonormal), the column rotated by the stored Givens rotations, the rotation that
 // removes h_{j+1,j}, and the residual estimate |g[j+1]|.  The cycle ends at m columns, at
 // the tolerance, at maxit or on a breakdown.
-__global__ __launch_bounds__(WG) void k_arn_reduce(int pass, VecLaunch a, const int* sys_part, const int* sys_nchunks,
-                                                   int m) {
-  __shared__ double lds[WG];
+__global__ __launch_bounds__(RWG) void k_arn_reduce(int pass, VecLaunch a, const int* sys_part, const int* sys_nchunks,
+                                                    int m) {
+  __shared__ double lds[RWG];
   const int sys = blockIdx.x;
   if (a.skip[sys]) return;
   SysState& S = a.sys[sys];
@@ -353,7 +353,7 @@ void launch_arn_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st)
 void launch_arn_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_arn_dots, a, grid, st); }
 void launch_arn_reduce(int pass, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks, int m,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_arn_reduce, dim3(nsys), dim3(WG), 0, st, pass, a, sys_part, sys_nchunks, m);
+  hipLaunchKernelGGL(k_arn_reduce, dim3(nsys), dim3(RWG), 0, st, pass, a, sys_part, sys_nchunks, m);
 }
 void launch_arn_update1(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_arn_update1, a, grid, st); }
 void launch_arn_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_arn_update, a, grid, st); }

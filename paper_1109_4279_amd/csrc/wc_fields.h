@@ -78,6 +78,7 @@ WC_D uint32_t gld_u32(const void* p, size_t i) { return ((gptr_t<uint32_t>)p)[i]
 WC_D int gld_i32(const void* p, size_t i) { return ((gptr_t<int>)p)[i]; }
 WC_D short gld_s16(const void* p, size_t i) { return ((gptr_t<short>)p)[i]; }
 WC_D float gld_f(const void* p, size_t i) { return ((gptr_t<float>)p)[i]; }
+WC_D double gld_d(const void* p, size_t i) { return ((gptr_t<double>)p)[i]; }
 
 // ------------------------------------------------------------------ spinors
 

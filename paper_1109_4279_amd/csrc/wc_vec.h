@@ -46,20 +46,33 @@ template <int NV> WC_D void put_partial(const VecLaunch& a, const VecSite& v, do
   }
 }
 
+// Threads of the per-system reduction kernels (one work-group per system).
+constexpr int RWG = 1024;
+
 // Per-system sums of the first nv values of the nc chunk partials starting at p0
-// (nv <= pw).  The work-group splits into groups of nvp = next power of two >= nv lanes;
-// lane j of group g adds value j of chunks g, g + groups, ..., so consecutive lanes read
-// consecutive words, and the groups are then added by a fixed tree.  Every thread of the
-// work-group calls this (lds: WG doubles); afterwards lds[j] holds the sum of value j.
+// (nv <= pw <= RWG).  The work-group splits into groups of nvp = next power of two >= nv
+// lanes; lane j of group g adds value j of chunks g, g + groups, ... into four independent
+// accumulators (chunk index mod 4 groups), so consecutive lanes read consecutive words and
+// four loads per lane are in flight; the accumulators and then the groups are added by a
+// fixed tree.  Every thread of the RWG-thread work-group calls this (lds: RWG doubles);
+// afterwards lds[j] holds the sum of value j.
 WC_D void sum_partials(const double* partials, int pw, long long p0, int nc, int nv, double* lds) {
   int nvp = 1;
   while (nvp < nv) nvp <<= 1;
-  const int groups = WG / nvp;
+  const int groups = RWG / nvp;
   const int t = threadIdx.x, j = t % nvp, grp = t / nvp;
-  double acc = 0.0;
-  if (j < nv)
-    for (int c = grp; c < nc; c += groups) acc += partials[(size_t)(p0 + c) * pw + j];
-  lds[t] = acc;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  if (j < nv) {
+    int c = grp;
+    for (; c + 3 * groups < nc; c += 4 * groups) {
+      acc0 += gld_d(partials, (size_t)(p0 + c) * pw + j);
+      acc1 += gld_d(partials, (size_t)(p0 + c + groups) * pw + j);
+      acc2 += gld_d(partials, (size_t)(p0 + c + 2 * groups) * pw + j);
+      acc3 += gld_d(partials, (size_t)(p0 + c + 3 * groups) * pw + j);
+    }
+    for (; c < nc; c += groups) acc0 += gld_d(partials, (size_t)(p0 + c) * pw + j);
+  }
+  lds[t] = (acc0 + acc1) + (acc2 + acc3);
   __syncthreads();
   for (int step = groups >> 1; step > 0; step >>= 1) {
     if (grp < step) lds[t] += lds[t + step * nvp];
