@@ -343,6 +343,9 @@ def main():
                     "frac_hbm": gbs / HBM_PEAK_GBS}
     # dominant kernel of the step: the FP32 Schwarz half-sweep (one colour, 4 steps of the
     # even/odd block solver); the unpreconditioned block solver's half-sweep beside it
+    # the same half-sweep with no MR step: loads, border update, source and odd half, stores
+    # (timed first, so that the last dispatches of the kernel in a profile are the nmr-step ones)
+    ms_sap0 = lat.bench_sap(prec="f32", nrhs=1, nmr=0, eo=True, iters=20 if args.profile else 100)
     ms_sap = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, eo=True, iters=20 if args.profile else 100)
     ms_sap_mr = lat.bench_sap(prec="f32", nrhs=1, nmr=NMR, eo=False, iters=20 if args.profile else 100)
     sites = V // 2
@@ -356,6 +359,17 @@ def main():
                 "hbm_GBps_alg": sap_bytes / (ms_sap * 1e-3) / 1e9,
                 "frac_of_packed_fp32_peak": tf / FP32_PEAK_TFLOPS,
                 "plain_mr_half_sweep_ms": ms_sap_mr}
+    # two phases of the launch: every HBM byte moves in the set-up and the stores (nmr = 0
+    # time); the MR steps run from registers and LDS (time per step from the difference)
+    step_ms = (ms_sap - ms_sap0) / NMR
+    step_flops = (DW_FLOPS + MR_VEC_FLOPS / 2) * sites
+    setup_bytes = roofline["traffic"] if roofline["traffic"] else sap_bytes
+    roofline["phases"] = {
+        "setup_ms": ms_sap0, "step_ms": step_ms,
+        "setup_GBps": setup_bytes / (ms_sap0 * 1e-3) / 1e9,
+        "setup_bytes": "measured traffic" if roofline["traffic"] else "algorithmic",
+        "step_TFLOPs": step_flops / (step_ms * 1e-3) / 1e12,
+        "step_frac": step_flops / (step_ms * 1e-3) / 1e12 / FP32_SCALAR_PEAK_TFLOPS}
 
     extras = {}
     if not args.profile and not args.no_extras:

@@ -438,16 +438,6 @@ static int sap_cache_mode(int nitems) {
   return nitems <= 2 * device_cus() ? 1 : 0;
 }
 
-// The one-lane-per-site block solver is the default; WC_SAP_KERNEL=3 selects the
-// colour-split kernel for FP32 arithmetic with one rhs per work-group.
-static bool sap_colour_split(int prec, int nr) {
-  static int forced = -2;
-  if (forced == -2) {
-    const char* e = getenv("WC_SAP_KERNEL");
-    forced = e ? atoi(e) : -1;
-  }
-  return forced == 3 && prec != P_F64 && nr == 1;
-}
 
 // odd_rho: residual on odd sites for the even/odd solver (see SapLaunch::odd_rho)
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
@@ -456,7 +446,6 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
   require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
-  const bool split = sap_colour_split(prec, nr);
   const LatDesc* L = B.lats(prec, st, eo != 0);
   const ItemList& it = B.items_sap(colour, nr);
   SapLaunch a;
@@ -483,9 +472,6 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
     launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), B.max_bvol, st);
   else if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
     launch_sap_mr_lds(prec, nr, a, persistent_grid(it.n, 1), st);
-  else if (split)
-    launch_sap_mr3(prec, a, persistent_grid(it.n, 2), ((3 * B.max_bvol + 63) / 64) * 64, B.max_bvol,
-                   B.uniform_bvol, st);
   else
     launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), B.sap_threads(), st);
 }

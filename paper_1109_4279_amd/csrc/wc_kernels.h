@@ -50,10 +50,6 @@ struct SapLaunch {
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
-// one lane per (site, colour); FP32 arithmetic precisions, one rhs per work-group
-void launch_sap_mr3(int prec, const SapLaunch& a, int grid, int threads, int max_bvol, int uniform_bvol,
-                    hipStream_t st);
-size_t sap3_lds_bytes(int bvol);
 // 16-bit storage, 4^4 blocks: block operator staged in LDS and shared by nr (1 or 2) rhs
 void launch_sap_mr_lds(int prec, int nr, const SapLaunch& a, int grid, hipStream_t st);
 
