@@ -74,7 +74,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
       if (lane == 0) lds[wid * (4 * NKV_MAX + 4) + j] = x;
     };
     for (int l = 0; l < k; ++l) {
-      Spinor<double> cl = ld64(a.chi[l], v);
+      Spinor<double> cl = ld64_nt(a.chi[l], v);
       double are = 0.0, aim = 0.0, ere = 0.0, eim = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
     for (int l = 0; l < k; ++l) {
       const double2 al = S.a[l * NKV_MAX + k];
       const cplx<double> m = {-al.x, -al.y};
-      Spinor<double> cl = ld64(a.chi[l], v);
+      Spinor<double> cl = ld64_nt(a.chi[l], v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
