@@ -112,3 +112,22 @@ def test_geometry_errors():
     assert e.value.code == -2
     with pytest.raises(wc.WCError):
         wc.Lattice(U, block=(3, 2, 2, 2))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+def test_dirac_on_links_outside_su3(prec):
+    """Links moved off SU(3) (a random 5 % perturbation; nothing in the storage may assume
+    unitarity, e.g. rebuild a row from the other two): D_w and D_Lambda match the oracle on
+    the field as given, in every storage precision."""
+    import paper_1109_4279_amd as wc
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    rng = np.random.default_rng(17)
+    U = synth.gauge_field(dims)
+    U = U + 0.05 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    A = dirac.clover_matrix(U, m0, csw)
+    lat = wc.Lattice(to_dev(U), block=block, m0=m0, csw=csw)
+    x = synth.gaussian_spinor(dims, nrhs=2, seed=9)
+    got = to_np(lat.apply_D(to_dev(x), prec=prec))
+    assert rel(got, dirac.apply_D(U, A, x)) < TOL[prec]
+    got = to_np(lat.apply_D(to_dev(x), prec=prec, region="blocks"))
+    assert rel(got, dirac.apply_D(U, A, x, block=block)) < TOL[prec]
