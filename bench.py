@@ -282,8 +282,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the 24^3x48 batch and 32^3x64 workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding design is "
-              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (sharding the lattice "
+              "into sub-lattices with one halo exchange per Schwarz half-sweep is not implemented); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
