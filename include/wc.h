@@ -71,6 +71,7 @@ typedef struct {
   int nr_dirac;  /* right-hand sides per lane in D (0: library / autotuned choice) */
   int nr_sap;    /* right-hand sides per work-group in the block solver (0: library choice) */
   int eo;        /* 1: even/odd-preconditioned block solver (Sec. 4, Table 1), 0: MR on D_Lambda */
+  int dagger;    /* 1: solve D^dag x = b, as g5 D^-1 g5 (gamma5-hermiticity of D); 0: D x = b */
 } wc_solver_params;
 
 typedef struct {

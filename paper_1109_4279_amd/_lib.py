@@ -21,7 +21,7 @@ class SolverParams(ctypes.Structure):
         ("nkv", ctypes.c_int), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
         ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("x0_given", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("nr_dirac", ctypes.c_int), ("nr_sap", ctypes.c_int),
-        ("eo", ctypes.c_int),
+        ("eo", ctypes.c_int), ("dagger", ctypes.c_int),
     ]
 
 

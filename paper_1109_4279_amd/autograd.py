@@ -1,6 +1,8 @@
 """torch.autograd.Functions around the library's operator, solve and pseudofermion action.
 
-All arithmetic (forward and backward) runs in libwc; these classes only route tensors:
+Every application of D, D^dag, D^-1 and D^-dag and every link derivative runs in libwc;
+torch only forms the action's value |Y|^2 from the library's Y and scales X by 2 dS in
+its backward.  These classes route tensors:
 
 * ``dirac_apply(U, x)``  y = D[U] x;  backward: dx = D^dag dy = g5 D g5 dy,
   dU = link derivative of Re<dy, D x> (torch's conjugate-gradient convention).
@@ -28,10 +30,13 @@ def _opts(block, m0, csw, bc_t):
     return {"block": tuple(block), "m0": float(m0), "csw": float(csw), "bc_t": int(bc_t)}
 
 
-def _g5(v):
-    out = v.clone()
-    out[..., 2:, :] *= -1
-    return out
+def _adjoint(params):
+    """A copy of the solver parameters that solves D^dag x = b."""
+    if params.dagger:
+        raise ValueError("the autograd functions solve with D; pass params with dagger = 0")
+    q = type(params).from_buffer_copy(params)
+    q.dagger = 1
+    return q
 
 
 class DiracApply(torch.autograd.Function):
@@ -56,9 +61,10 @@ class DiracApply(torch.autograd.Function):
 class DiracSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, b, opts, params):
+        adj = _adjoint(params)
         lat = _lattice(U, opts)
         x, _ = lat.solve(b.detach().contiguous(), params=params)
-        ctx.lat, ctx.params = lat, params
+        ctx.lat, ctx.adj = lat, adj
         ctx.save_for_backward(x)
         return x
 
@@ -66,9 +72,7 @@ class DiracSolve(torch.autograd.Function):
     def backward(ctx, gx):
         (x,) = ctx.saved_tensors
         lat = ctx.lat
-        # db = D^-dag gx = g5 D^-1 g5 gx
-        y, _ = lat.solve(_g5(gx.contiguous()), params=ctx.params)
-        gb = _g5(y)
+        gb, _ = lat.solve(gx.contiguous(), params=ctx.adj)  # db = D^-dag gx
         gU = lat.link_grad(gb, x, coef=-1.0) if ctx.needs_input_grad[0] else None
         return gU, (gb if ctx.needs_input_grad[1] else None), None, None
 
@@ -76,10 +80,9 @@ class DiracSolve(torch.autograd.Function):
 class PseudofermionAction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, phi, opts, params):
+        adj = _adjoint(params)
         lat = _lattice(U, opts)
-        phic = phi.detach().contiguous()
-        y, _ = lat.solve(_g5(phic), params=params)
-        Y = _g5(y)
+        Y, _ = lat.solve(phi.detach().contiguous(), params=adj)  # Y = D^-dag phi
         X, _ = lat.solve(Y, params=params)
         ctx.lat = lat
         ctx.save_for_backward(Y, X)

@@ -20,6 +20,7 @@ namespace wc {
 void launch_force(const int* L, int bc_t, const void* Ucanon, const void* Y, const void* X, int nrhs, double csw,
                   double coef, int out_kind, void* xi_work, void* out, hipStream_t st);
 void launch_gamma5_canon(long long nsite, const void* src, void* dst, hipStream_t st);
+void launch_gamma5_f64(void* f, long long V, int nrhs, hipStream_t st);
 void launch_clover_export(const Geom& g, const void* c64, void* out, hipStream_t st);
 void launch_fill_hash(long long n, unsigned seed, void* out, hipStream_t st);
 
@@ -1073,6 +1074,7 @@ void wc_default_params(wc_solver_params* p) {
   p->nr_dirac = 0;
   p->nr_sap = 0;
   p->eo = 0;
+  p->dagger = 0;
 }
 
 int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const void* U, int bc_t, void* stream) {
@@ -1230,11 +1232,25 @@ static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<
       prepare_solver(*B, s);
     pack_batch(*B, P_F64, b, B->b, st);
     if (p->x0_given) pack_batch(*B, P_F64, (const void* const*)x, B->x, st);
+    // D^dag x = b  <=>  D (g5 x) = g5 b
+    auto gamma5 = [&](Field& f) {
+      long long off = 0;
+      for (size_t i = 0; i < B->lat.size(); ++i) {
+        const long long V = B->lat[i]->g.V;
+        launch_gamma5_f64((double2*)f.data() + off * 12, V, B->nrhs[i], st);
+        off += (long long)B->nrhs[i] * V;
+      }
+    };
+    if (p->dagger) {
+      gamma5(B->b);
+      if (p->x0_given) gamma5(B->x);
+    }
     std::vector<wc_solver_stats> stats;
     if (kdefl >= 0)
       rc = fgmres_dr_solve(*B, s, kdefl, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
     else
       rc = fgcr_solve(*B, s, p->x0_given != 0, p->use_graph != 0, ctxs[0], stats, st);
+    if (p->dagger) gamma5(B->x);
     unpack_batch(*B, P_F64, B->x, x, -1, st);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(st));
@@ -1325,6 +1341,7 @@ int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_
     // Y = D^-dag phi = g5 D^-1 g5 phi (gamma5-hermiticity), then X = D^-1 Y
     wc_solver_params q = *p;
     q.x0_given = 0;
+    q.dagger = 0;
     wc_solver_stats s2[2];
     launch_gamma5_canon(c->g.V, phi, tmp.p, st_);
     int r1 = wc_fgcr_solve(c, y.p, tmp.p, 1, &q, &s2[0], stream);
@@ -1496,6 +1513,7 @@ int wc_autotune_block(wc_ctx* c, const wc_solver_params* p, int block_out[4], vo
       layout(c, b.data(), st);
       wc_solver_params q = *p;
       q.x0_given = 0;
+      q.dagger = 0;
       wc_solver_stats sst;
       // first solve builds graphs and buffers; the second is timed
       int rc = wc_fgcr_solve(c, xsol.p, bsrc.p, 1, &q, &sst, stream);

@@ -438,6 +438,21 @@ __global__ __launch_bounds__(WG) void k_gamma5_canon(long long nsite, const doub
   }
 }
 
+// gamma5 in place on nrhs FP64 fields of the library's layout ([12][V] double2 each): the
+// components of the lower two spins (6..11) change sign
+__global__ __launch_bounds__(WG) void k_gamma5_f64(double2* f, long long V, int nrhs) {
+  const long long e = (long long)blockIdx.x * WG + threadIdx.x;
+  if (e >= 6 * V * nrhs) return;
+  const long long r = e / (6 * V), k = e - r * 6 * V;
+  double2& v = f[r * 12 * V + 6 * V + k];
+  v = make_double2(-v.x, -v.y);
+}
+
+void launch_gamma5_f64(void* f, long long V, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((6 * V * nrhs + WG - 1) / WG));
+  hipLaunchKernelGGL(k_gamma5_f64, grid, dim3(WG), 0, st, (double2*)f, V, nrhs);
+}
+
 void launch_gamma5_canon(long long nsite, const void* src, void* dst, hipStream_t st) {
   dim3 grid((unsigned)((nsite + WG - 1) / WG));
   hipLaunchKernelGGL(k_gamma5_canon, grid, dim3(WG), 0, st, nsite, (const double2*)src, (double2*)dst);

@@ -52,12 +52,27 @@ def test_binding_argument_counts_match_header():
         assert len(args) == counts[name], name
 
 
+def _struct_fields(name):
+    """Field names of the C struct `name` in include/wc.h, in declaration order."""
+    src = open(os.path.join(ROOT, "include", "wc.h")).read()
+    end = re.search(r"\}\s*" + name + ";", src).start()
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return [re.findall(r"(\w+)\s*$", d.strip())[0] for d in body.split(";") if d.strip()]
+
+
+def test_binding_structs_match_header():
+    from paper_1109_4279_amd import _lib
+    assert [f for f, _ in _lib.SolverParams._fields_] == _struct_fields("wc_solver_params")
+    assert [f for f, _ in _lib.SolverStats._fields_] == _struct_fields("wc_solver_stats")
+
+
 def test_default_params_and_error_text():
     from paper_1109_4279_amd import _lib, default_params
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("libwc.so not built")
     p = default_params()
-    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo) == (16, 5, 4, 1, 10000, 0)
+    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo, p.dagger) == (16, 5, 4, 1, 10000, 0, 0)
     assert abs(p.tol - 1e-10) < 1e-25
     lib = _lib.load()
     # argument errors are reported without touching a device

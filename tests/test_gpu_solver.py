@@ -120,3 +120,37 @@ def test_not_converged_and_breakdown_reported():
     bn[0, 0, 0, 0, 0, 0] = float("nan")
     x, st = lat.solve(bn, tol=1e-10, check=False)
     assert st[0]["status"] in (-6, -5)
+
+
+@pytest.mark.parametrize("k", [None, 3])
+def test_adjoint_solve(k):
+    """dagger = 1 solves D^dag x = b (as g5 D^-1 g5): the oracle's D^dag reproduces b to
+    1e-10, from zero and from a given initial guess, with FGCR (k None) and FGMRES-DR."""
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    U, A = gauge(dims), clover(dims, m0, csw)
+    b = synth.gaussian_spinor(dims, nrhs=2, seed=71)
+    kw = dict(tol=1e-10, sap_prec="f32", dagger=1, nkv=8)
+
+    def solve(rhs, x0=None):
+        if k is None:
+            return lat.solve(to_dev(rhs), x0=x0, **kw)
+        return lat.solve_fgmres_dr(to_dev(rhs), k=k, x0=x0, **kw)
+
+    def res(x, r):
+        return dirac.norm(b[r] - dirac.apply_Ddag(U, A, x[r])) / dirac.norm(b[r])
+
+    x, st = solve(b)
+    x = to_np(x)
+    for r in range(2):
+        assert st[r]["status"] == 0
+        assert res(x, r) <= 1e-10
+        assert res(x, r) == pytest.approx(st[r]["rel_true_res"], rel=1e-3, abs=1e-14)
+    # not the solution of D x = b
+    assert dirac.norm(b[0] - dirac.apply_D(U, A, x[0])) / dirac.norm(b[0]) > 1e-3
+    x0 = x + 1e-4 * synth.gaussian_spinor(dims, nrhs=2, seed=72)
+    x1, st1 = solve(b, x0=to_dev(x0))
+    x1 = to_np(x1)
+    for r in range(2):
+        assert st1[r]["status"] == 0 and res(x1, r) <= 1e-10
+        assert st1[r]["iters"] < st[r]["iters"]
