@@ -43,6 +43,12 @@ def _need(t, name, shape_tail=None):
     return t
 
 
+def _params(params, kw):
+    """The caller's parameters (copied: the solve sets x0_given on its copy) or defaults
+    updated by kw."""
+    return SolverParams.from_buffer_copy(params) if params is not None else default_params(**kw)
+
+
 def default_params(**kw) -> SolverParams:
     p = SolverParams()
     _lib.load().wc_default_params(ctypes.byref(p))
@@ -132,7 +138,7 @@ class Lattice:
     def solve(self, b, params: SolverParams | None = None, x0=None, stream=None, check=True, **kw):
         """x = D^-1 b by SAP-preconditioned FGCR.  Returns (x, list of per-rhs stats dicts)."""
         nrhs = self._spinor(b, "b")
-        p = params if params is not None else default_params(**kw)
+        p = _params(params, kw)
         if x0 is not None:
             x = x0.clone()
             p.x0_given = 1
@@ -151,7 +157,7 @@ class Lattice:
         harmonic Ritz vectors kept at every restart (k = 0: restarted FGMRES).  Returns
         (x, list of per-rhs stats dicts)."""
         nrhs = self._spinor(b, "b")
-        p = params if params is not None else default_params(**kw)
+        p = _params(params, kw)
         if x0 is not None:
             x = x0.clone()
             p.x0_given = 1
@@ -226,7 +232,7 @@ def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, c
     bs[i] is a complex128 [nrhs_i][dims_i][4][3] tensor.  Returns (xs, stats)."""
     lib = _lib.load()
     n = len(lattices)
-    p = params if params is not None else default_params(**kw)
+    p = _params(params, kw)
     p.x0_given = 0
     xs, nr = [], []
     for lat, b in zip(lattices, bs):
