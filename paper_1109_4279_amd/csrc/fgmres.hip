@@ -178,6 +178,11 @@ __global__ __launch_bounds__(WG) void k_arn_update1(VecLaunch a) {
 __global__ __launch_bounds__(RWG) void k_arn_reduce(int pass, VecLaunch a, const int* sys_part, const int* sys_nchunks,
                                                     int m) {
   __shared__ double lds[RWG];
+  // the stored rotations and the new column, for the serial work of thread 0
+  __shared__ double rot_c[ARN_ROT_MAX];
+  __shared__ double2 rot_s[ARN_ROT_MAX];
+  __shared__ int rot_p[ARN_ROT_MAX];
+  __shared__ double2 cc[ARN_LD];
   const int sys = blockIdx.x;
   if (a.skip[sys]) return;
   SysState& S = a.sys[sys];
@@ -185,6 +190,14 @@ __global__ __launch_bounds__(RWG) void k_arn_reduce(int pass, VecLaunch a, const
   const int j = a.k;
   const int nv = 2 * (j + 1) + 1;
   sum_partials(a.partials, a.pw, sys_part[sys], sys_nchunks[sys], nv, lds);
+  if (pass != 1) {
+    for (int q = threadIdx.x; q < A.nrot; q += RWG) {
+      rot_c[q] = A.rc[q];
+      rot_s[q] = A.rs[q];
+      rot_p[q] = A.rp[q];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
   const double* sum = lds;
   if (pass == 1) {
@@ -215,12 +228,11 @@ __global__ __launch_bounds__(RWG) void k_arn_reduce(int pass, VecLaunch a, const
   A.lucky = lucky;
   // rotate a copy of the new column by the stored rotations (Hbar itself stays unrotated
   // for the host's least squares), then add the rotation that removes h_{j+1,j}
-  double2 cc[ARN_LD];
   for (int i = 0; i <= j + 1; ++i) cc[i] = col[i];
   for (int q = 0; q < A.nrot; ++q) {
-    const int p = A.rp[q];
-    const double c = A.rc[q];
-    const double2 s = A.rs[q];
+    const int p = rot_p[q];
+    const double c = rot_c[q];
+    const double2 s = rot_s[q];
     const double2 x = cc[p], y = cc[p + 1];
     // x' = c x + s y ; y' = -conj(s) x + c y
     cc[p] = make_double2(c * x.x + s.x * y.x - s.y * y.y, c * x.y + s.x * y.y + s.y * y.x);
