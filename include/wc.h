@@ -84,7 +84,7 @@ typedef struct {
 } wc_solver_stats;
 
 /* Fill p with the library defaults: nkv 16, ncy 5, nmr 4, sap_prec WC_F32, tol 1e-10,
- * maxit 10000, no initial guess, graphs on, automatic RHS tiles. */
+ * maxit 10000, no initial guess, graphs on, automatic RHS tiles, MR block solver, D x = b. */
 void wc_default_params(wc_solver_params* p);
 
 /* Create a context for one lattice: copies the gauge field U (device, complex128, see
@@ -126,7 +126,8 @@ int wc_sap_block_mr(wc_ctx* ctx, void* z, void* rho, int nrhs, int colour, int n
  * eo selects the block solver as for wc_sap_block_mr. */
 int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, int prec, int eo, void* stream);
 
-/* Solve D x = b for nrhs right-hand sides with SAP-preconditioned restarted FGCR (Sec. 4).
+/* Solve D x = b (D^dag x = b when p->dagger) for nrhs right-hand sides with
+ * SAP-preconditioned restarted FGCR (Sec. 4).
  * The preconditioner runs in p->sap_prec; chi = D phi, Gram-Schmidt, the residual update,
  * the solution update and the true residual stay in FP64.  st (may be NULL) receives nrhs
  * entries.  Synchronises `stream` once per restart.  Returns WC_OK when every rhs
