@@ -1,7 +1,7 @@
 """Wilson-Dirac operator with clover term, FP64 reference (oracle; test infrastructure only).
 
-Follows the operator named in the abstract and Sec. 4 of arXiv:1109.4279
-("Wilson-Dirac solver with Clover term"), which the paper does not write out.
+Follows the operator named in the abstract and Sec. 4 of arXiv:1109.4279 (the Wilson-Dirac
+operator with clover term), which the paper does not write out.
 The form used, with the paper silent on every convention, is
 
     D psi(x) = A(x) psi(x)

@@ -87,7 +87,7 @@ def sap(U, A, eta, block, nmr: int, ncy: int, bc_t: int = 1, eo: bool = False):
     The residual update is written as its definition rho <- rho - D z: z lives on the blocks
     just solved, so this leaves the MR residual on those blocks and subtracts the hops out of
     them on the border sites of the opposite-colour blocks, which is the update the paper
-    describes ("on the internal border of the black blocks").
+    describes for the sites just inside the other colour's blocks.
 
     eo selects the even/odd-preconditioned block solver ``mr_blocks_eo``."""
     check_blocking(lattice_dims(eta), block)
