@@ -11,7 +11,9 @@ the solve divided by the step time).  Beside it: the FP64 solve time on the same
 (with the same block solver and with MR on the unpreconditioned block operator), the
 mixed solve with the unpreconditioned block solver, D_w GB/s and Gflop/s per storage
 precision against the 8 TB/s HBM roofline, the roofline record of the dominant kernel
-(the Schwarz block solver, bound by vector ALU), the batched 12-point-source solve on
+(the Schwarz block solver against the vector-ALU peak, with its two phases: the set-up that
+moves the operator and the fields, and the MR steps that run from registers and LDS),
+the batched 12-point-source solve on
 24^3 x 48 against 12 single FP64 solves, the 32^3 x 64 solve on 16-bit storage, FGCR
 against FGMRES-DR close to the critical mass (the regime of the paper's Fig. 1), and the
 FP64 oracle timed on the host for a bounded sample of the same workload.
