@@ -4,8 +4,8 @@
 // One work-group per block (tile) and right-hand-side group, one lane per site.
 // Before the MR steps the residual of the block is brought up to date with the hops
 // out of the neighbouring blocks of the other colour, whose latest block solutions z
-// are in memory: the "residue update on the internal border" of the paper, done as a
-// gather so that no two work-groups write the same site.  Then nmr MR steps on the
+// are in memory: the paper's residual update on the border sites of the blocks, done as
+// a gather so that no two work-groups write the same site.  Then nmr MR steps on the
 // Dirichlet block operator run with the block residual exchanged through LDS:
 //   q = D_Lambda rho,  alpha = <q, rho>/<q, q>,  z += alpha rho,  rho -= alpha q.
 // The inner products are work-group reductions (wavefront shuffles + LDS).
