@@ -59,6 +59,25 @@ def test_fgcr_antiperiodic_and_initial_guess():
     assert np.array_equal(to_np(x2), to_np(x))
 
 
+@pytest.mark.parametrize("sap_prec,eo", [("f32", 0), ("f16", 1)])
+def test_fgcr_source_scale(sap_prec, eo):
+    """The preconditioner sees the residual divided by its norm, so the solve is equivariant
+    under scaling of b: with b scaled by 2^-300 or 2^300 (far outside FP32 and FP16; a power
+    of two, so every FP64 rounding scales exactly) x is the unscaled solution times the same
+    factor, bit for bit, after the same number of iterations."""
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims, seed=43)
+    x1, st1 = lat.solve(to_dev(b), tol=1e-10, sap_prec=sap_prec, eo=eo)
+    x1 = to_np(x1)
+    assert st1[0]["status"] == 0
+    for e in (-300, 300):
+        s = np.ldexp(1.0, e)
+        xs, sts = lat.solve(to_dev(b * s), tol=1e-10, sap_prec=sap_prec, eo=eo)
+        assert sts[0]["status"] == 0 and sts[0]["iters"] == st1[0]["iters"]
+        assert np.array_equal(to_np(xs), x1 * s)
+
+
 def test_fgcr_multi_rhs_point_sources():
     dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
     lat = lattice(dims, block, m0, csw)
