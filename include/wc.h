@@ -130,8 +130,9 @@ int wc_sap(wc_ctx* ctx, void* psi, const void* eta, int nrhs, int ncy, int nmr, 
  * SAP-preconditioned restarted FGCR (Sec. 4).
  * The preconditioner runs in p->sap_prec; chi = D phi, Gram-Schmidt, the residual update,
  * the solution update and the true residual stay in FP64.  st (may be NULL) receives nrhs
- * entries.  Synchronises `stream` once per restart.  Returns WC_OK when every rhs
- * converged, else the first failing status (x is written regardless). */
+ * entries.  Synchronises `stream` once per restart.  A right-hand side with b = 0 returns
+ * x = 0 after zero iterations, also when an initial guess was given.  Returns WC_OK when
+ * every rhs converged, else the first failing status (x is written regardless). */
 int wc_fgcr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_solver_params* p, wc_solver_stats* st,
                   void* stream);
 

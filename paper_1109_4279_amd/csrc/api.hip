@@ -621,6 +621,7 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
   launch_norm2(va, B.b.d.as<double2>(), gv, st);
   launch_reduce(RED_BNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   if (x0_given) {
+    launch_zero_if_b0(va, B.x.d.as<double2>(), gv, st);
     run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
     launch_reduce(RED_INITR, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   } else {
@@ -832,6 +833,7 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
   launch_norm2(va, B.b.d.as<double2>(), gv, st);
   launch_reduce(RED_BNORM, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   if (x0_given) {
+    launch_zero_if_b0(va, B.x.d.as<double2>(), gv, st);
     run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
     launch_reduce(RED_INITR, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   } else {

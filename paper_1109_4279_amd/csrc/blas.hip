@@ -197,6 +197,21 @@ __global__ __launch_bounds__(WG) void k_copy(VecLaunch a, double2* dst, const do
   }
 }
 
+// x = 0 on the systems whose source is zero (|b|^2 from the preceding reduction): their
+// only solution, reached before any iteration whatever initial guess was given.
+__global__ __launch_bounds__(WG) void k_zero_if_b0(VecLaunch a, double2* x) {
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (!v.valid || a.sys[v.sys].bnorm2 != 0.0) continue;
+    Spinor<double> z;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) z.c[i][c] = {0.0, 0.0};
+    st64(x, v, z);
+  }
+}
+
 // ------------------------------------------------------------------ per-system reductions
 
 __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
@@ -327,6 +342,9 @@ void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st
 }
 void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(WG), 0, st, a, dst, src);
+}
+void launch_zero_if_b0(const VecLaunch& a, double2* x, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_if_b0, dim3(grid), dim3(WG), 0, st, a, x);
 }
 void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
                    hipStream_t st) {

@@ -138,6 +138,7 @@ void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);   // chi_k 
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials
 void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st);
+void launch_zero_if_b0(const VecLaunch& a, double2* x, int grid, hipStream_t st);  // x = 0 where |b| = 0
 
 // per-system reductions and scalar steps (one work-group per system)
 enum ReduceOp { RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5 };

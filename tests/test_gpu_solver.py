@@ -173,3 +173,28 @@ def test_adjoint_solve(k):
     for r in range(2):
         assert st1[r]["status"] == 0 and res(x1, r) <= 1e-10
         assert st1[r]["iters"] < st[r]["iters"]
+
+
+@pytest.mark.parametrize("k", [None, 3])
+def test_zero_source(k):
+    """b = 0 has the one solution x = 0: returned converged after zero iterations beside a
+    non-zero rhs of the same solve, from zero and from a non-zero initial guess, with FGCR
+    (k None) and FGMRES-DR."""
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims, nrhs=2, seed=44)
+    b[0] = 0.0
+    kw = dict(tol=1e-10, sap_prec="f32", nkv=8)
+
+    def solve(x0=None):
+        if k is None:
+            return lat.solve(to_dev(b), x0=x0, **kw)
+        return lat.solve_fgmres_dr(to_dev(b), k=k, x0=x0, **kw)
+
+    for x0 in (None, to_dev(synth.gaussian_spinor(dims, nrhs=2, seed=45))):
+        x, st = solve(x0)
+        x = to_np(x)
+        assert st[0]["status"] == 0 and st[0]["iters"] == 0
+        assert not x[0].any()
+        assert st[1]["status"] == 0
+        assert _true_res(dims, m0, csw, x[1], b[1]) <= 1e-10
