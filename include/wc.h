@@ -27,6 +27,10 @@
  * Streams      `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
  *              it; only the solver entry points synchronise (once per FGCR restart, to
  *              read the residual norms) and say so.
+ * Concurrency  a context owns work fields and a capture stream that its calls reuse: two
+ *              calls naming the same context (batched calls included) must not overlap,
+ *              whether from two host threads or on two streams without ordering between
+ *              them.  Calls on distinct contexts are independent.
  * Errors       every int-returning function returns WC_OK (0) or a negative wc_status;
  *              wc_last_error() gives a message for the calling thread.  Nothing throws
  *              across this interface.  On an error no output has been written unless

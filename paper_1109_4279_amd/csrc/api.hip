@@ -43,6 +43,38 @@ static void require(bool ok, int code, const std::string& msg) {
   if (!ok) throw Error{code, msg};
 }
 
+// HIP event released on every exit path (HIPCK throws)
+struct HipEvent {
+  hipEvent_t e = nullptr;
+  HipEvent() { HIPCK(hipEventCreate(&e)); }
+  ~HipEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  HipEvent(const HipEvent&) = delete;
+  HipEvent& operator=(const HipEvent&) = delete;
+  operator hipEvent_t() const { return e; }
+};
+
+// Instantiated graph of what f enqueues on the capture stream `cap`.  If f throws, the
+// capture is ended and its partial graph dropped, so `cap` leaves capture mode.
+static hipGraphExec_t capture_graph(hipStream_t cap, const std::function<void(hipStream_t)>& f) {
+  HIPCK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  try {
+    f(cap);
+  } catch (...) {
+    hipGraph_t partial = nullptr;
+    if (hipStreamEndCapture(cap, &partial) == hipSuccess && partial) (void)hipGraphDestroy(partial);
+    throw;
+  }
+  hipGraph_t graph;
+  HIPCK(hipStreamEndCapture(cap, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t instantiate = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCK(instantiate);
+  return exec;
+}
+
 // owning device allocation
 struct DevBuf {
   void* p = nullptr;
@@ -611,9 +643,7 @@ static std::string setup_key(const SolveSetup& s) {
 
 static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_graph, wc_ctx* cap_owner,
                       std::vector<wc_solver_stats>& stats, hipStream_t st) {
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
+  HipEvent e0, e1;
   HIPCK(hipEventRecord(e0, st));
   VecLaunch va = vec_launch(B, s, st);
   const int gv = persistent_grid(va.nitems, 8);
@@ -641,12 +671,7 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
         B.graph = nullptr;
       }
       if (!cap_owner->cap) HIPCK(hipStreamCreateWithFlags(&cap_owner->cap, hipStreamNonBlocking));
-      hipGraph_t graph;
-      HIPCK(hipStreamBeginCapture(cap_owner->cap, hipStreamCaptureModeThreadLocal));
-      enqueue_cycle(B, s, cap_owner->cap);
-      HIPCK(hipStreamEndCapture(cap_owner->cap, &graph));
-      HIPCK(hipGraphInstantiate(&B.graph, graph, nullptr, nullptr, 0));
-      HIPCK(hipGraphDestroy(graph));
+      B.graph = capture_graph(cap_owner->cap, [&](hipStream_t cs) { enqueue_cycle(B, s, cs); });
       B.graph_key = key;
       exec = B.graph;
     }
@@ -670,8 +695,6 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
   HIPCK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
 
   std::vector<SysState> hs(B.nsys);
   HIPCK(hipMemcpy(hs.data(), B.sys.p, sizeof(SysState) * B.nsys, hipMemcpyDeviceToHost));
@@ -823,9 +846,7 @@ static bool deflate_host(int mm, int k, ArnState& A, const std::vector<dense::cd
 static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_given, bool use_graph, wc_ctx* cap_owner,
                            std::vector<wc_solver_stats>& stats, hipStream_t st) {
   using dense::cd;
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
+  HipEvent e0, e1;
   HIPCK(hipEventRecord(e0, st));
   VecLaunch va = arn_launch(B, s, st);
   const int gv = persistent_grid(va.nitems, 8);
@@ -881,13 +902,8 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
       if (it == B.arn_graphs.end()) {
         if (!cap_owner->cap) HIPCK(hipStreamCreateWithFlags(&cap_owner->cap, hipStreamNonBlocking));
         HIPCK(hipStreamSynchronize(st));
-        hipGraph_t graph;
-        hipGraphExec_t exec;
-        HIPCK(hipStreamBeginCapture(cap_owner->cap, hipStreamCaptureModeThreadLocal));
-        enqueue_arn_cycle(B, s, j0, cap_owner->cap);
-        HIPCK(hipStreamEndCapture(cap_owner->cap, &graph));
-        HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        HIPCK(hipGraphDestroy(graph));
+        hipGraphExec_t exec =
+            capture_graph(cap_owner->cap, [&](hipStream_t cs) { enqueue_arn_cycle(B, s, j0, cs); });
         it = B.arn_graphs.emplace(key, exec).first;
       }
       HIPCK(hipGraphLaunch(it->second, st));
@@ -958,8 +974,6 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
   HIPCK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   get_sys();
   int rc = WC_OK;
   stats.resize(n);
@@ -1375,26 +1389,20 @@ static double time_launches(wc_ctx* c, hipStream_t st, int iters, const std::fun
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(st));
   if (!c->cap) HIPCK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  HIPCK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-  for (int i = 0; i < iters; ++i) f(c->cap);
-  HIPCK(hipStreamEndCapture(c->cap, &graph));
-  HIPCK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  HIPCK(hipGraphDestroy(graph));
-  hipEvent_t e0, e1;
-  HIPCK(hipEventCreate(&e0));
-  HIPCK(hipEventCreate(&e1));
-  HIPCK(hipGraphLaunch(exec, st));
+  struct Exec {
+    hipGraphExec_t g;
+    ~Exec() { (void)hipGraphExecDestroy(g); }
+  } exec{capture_graph(c->cap, [&](hipStream_t cs) {
+    for (int i = 0; i < iters; ++i) f(cs);
+  })};
+  HipEvent e0, e1;
+  HIPCK(hipGraphLaunch(exec.g, st));
   HIPCK(hipEventRecord(e0, st));
-  HIPCK(hipGraphLaunch(exec, st));
+  HIPCK(hipGraphLaunch(exec.g, st));
   HIPCK(hipEventRecord(e1, st));
   HIPCK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipGraphExecDestroy(exec);
   return double(ms) / iters;
 }
 
