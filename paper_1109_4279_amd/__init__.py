@@ -43,19 +43,32 @@ def _need(t, name, shape_tail=None):
     return t
 
 
-def _params(params, kw):
-    """The caller's parameters (copied: the solve sets x0_given on its copy) or defaults
-    updated by kw."""
-    return SolverParams.from_buffer_copy(params) if params is not None else default_params(**kw)
-
-
-def default_params(**kw) -> SolverParams:
-    p = SolverParams()
-    _lib.load().wc_default_params(ctypes.byref(p))
+def _set_fields(p, kw):
+    names = {f[0] for f in SolverParams._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver parameter {k!r} (fields: {', '.join(sorted(names))})")
         if k == "sap_prec" and isinstance(v, str):
             v = PREC[v]
         setattr(p, k, v)
+
+
+def _params(params, kw):
+    """A copy of the caller's parameters (the solve sets x0_given on its copy), or the
+    defaults, with the fields named in kw replaced."""
+    if params is None:
+        return default_params(**kw)
+    p = SolverParams.from_buffer_copy(params)
+    _set_fields(p, kw)
+    return p
+
+
+def default_params(**kw) -> SolverParams:
+    """The library's defaults (wc_default_params) with the fields named in kw replaced;
+    sap_prec may be given by name ("f64", "f32", "f16", "bf16")."""
+    p = SolverParams()
+    _lib.load().wc_default_params(ctypes.byref(p))
+    _set_fields(p, kw)
     return p
 
 
@@ -186,7 +199,7 @@ class Lattice:
         """Pseudofermion force of S = phi^dag (D^dag D)^-1 phi; returns (F, Y, X, stats)."""
         self._spinor(phi, "phi")
         torch = _torch()
-        p = params if params is not None else default_params(**kw)
+        p = _params(params, kw)
         F = torch.empty_like(self._U)
         Y = self.new_spinor()
         X = self.new_spinor()
@@ -201,7 +214,7 @@ class Lattice:
         return int(out[0]), int(out[1])
 
     def autotune_block(self, params: SolverParams | None = None, stream=None, **kw):
-        p = params if params is not None else default_params(**kw)
+        p = _params(params, kw)
         out = (ctypes.c_int * 4)()
         _lib.check(_lib.load().wc_autotune_block(self._ctx, ctypes.byref(p), out, _stream(stream)))
         self.block = tuple(int(v) for v in out)

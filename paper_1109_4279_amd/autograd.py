@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import torch
 
-from . import Lattice, default_params
+from . import Lattice, _params
 
 
 def _lattice(U, opts):
@@ -103,10 +103,10 @@ def dirac_apply(U, x, block=(4, 4, 4, 4), m0=0.0, csw=1.0, bc_t=1):
 
 
 def dirac_solve(U, b, block=(4, 4, 4, 4), m0=0.0, csw=1.0, bc_t=1, params=None, **kw):
-    p = params if params is not None else default_params(**kw)
+    p = _params(params, kw)
     return DiracSolve.apply(U, b, _opts(block, m0, csw, bc_t), p)
 
 
 def pseudofermion_action(U, phi, block=(4, 4, 4, 4), m0=0.0, csw=1.0, bc_t=1, params=None, **kw):
-    p = params if params is not None else default_params(**kw)
+    p = _params(params, kw)
     return PseudofermionAction.apply(U, phi, _opts(block, m0, csw, bc_t), p)

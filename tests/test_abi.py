@@ -85,6 +85,24 @@ def test_default_params_and_error_text():
     assert lib.wc_apply_D(None, None, None, 1, 0, 0, 0, None) == -1
 
 
+def test_solver_params_from_keywords():
+    """Keywords replace fields of the defaults or of a given parameter block (which is
+    copied, never changed); a name that is not a field is an error, not ignored."""
+    from paper_1109_4279_amd import _lib, _params, default_params
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwc.so not built")
+    p = default_params(nkv=8, sap_prec="f16")
+    assert (p.nkv, p.sap_prec) == (8, _lib.PREC["f16"])
+    q = _params(p, {"tol": 1e-8, "eo": 1})
+    assert (q.tol, q.eo, q.nkv) == (1e-8, 1, 8)
+    assert (p.tol, p.eo) == (1e-10, 0)
+    assert _params(None, {"nmr": 2}).nmr == 2
+    with pytest.raises(TypeError, match="tolerance"):
+        default_params(tolerance=1e-8)
+    with pytest.raises(TypeError, match="nvk"):
+        _params(p, {"nvk": 3})
+
+
 def test_product_package_does_not_import_the_oracle():
     pkg = os.path.join(ROOT, "paper_1109_4279_amd")
     for dirpath, _, files in os.walk(pkg):
