@@ -53,6 +53,11 @@ def _set_fields(p, kw):
         setattr(p, k, v)
 
 
+def _overlap(a, b):
+    pa, pb = a.data_ptr(), b.data_ptr()
+    return pa < pb + b.numel() * b.element_size() and pb < pa + a.numel() * a.element_size()
+
+
 def _params(params, kw):
     """A copy of the caller's parameters (the solve sets x0_given on its copy), or the
     defaults, with the fields named in kw replaced."""
@@ -107,10 +112,18 @@ class Lattice:
             self._ctx = None
 
     # ------------------------------------------------------------------ helpers
-    def _spinor(self, t, name):
+    def _spinor(self, t, name, like=None):
+        """Number of right-hand sides of a spinor argument: a complex128 tensor
+        [L0..L3][4][3] (one) or [nrhs][L0..L3][4][3] on the lattice's device; with `like`,
+        it must have like's shape.  Checked before the library sees the pointer."""
         _need(t, name, self.dims + (4, 3))
-        nrhs = 1 if t.dim() == 6 else int(t.numel() // (self.volume * 12))
-        return nrhs
+        if t.dim() not in (6, 7):
+            raise WCError(-1, f"{name} must be [L0..L3][4][3] or [nrhs][L0..L3][4][3], got {tuple(t.shape)}")
+        if t.device != self._U.device:
+            raise WCError(-1, f"{name} is on {t.device}, the lattice on {self._U.device}")
+        if like is not None and t.shape != like.shape:
+            raise WCError(-1, f"{name} has shape {tuple(t.shape)}, expected {tuple(like.shape)}")
+        return 1 if t.dim() == 6 else int(t.shape[0])
 
     def new_spinor(self, nrhs=None):
         torch = _torch()
@@ -120,7 +133,12 @@ class Lattice:
     # ------------------------------------------------------------------ operator
     def apply_D(self, x, prec="f64", region="full", dagger=False, out=None, stream=None):
         nrhs = self._spinor(x, "x")
-        out = self.new_spinor(None if x.dim() == 6 else nrhs) if out is None else out
+        if out is None:
+            out = self.new_spinor(None if x.dim() == 6 else nrhs)
+        else:
+            self._spinor(out, "out", like=x)
+            if _overlap(out, x):
+                raise WCError(-1, "out overlaps x")
         _lib.check(_lib.load().wc_apply_D(self._ctx, _ptr(out), _ptr(x), nrhs, PREC[prec], REGION[region],
                                           int(bool(dagger)), _stream(stream)))
         return out
@@ -153,6 +171,7 @@ class Lattice:
         nrhs = self._spinor(b, "b")
         p = _params(params, kw)
         if x0 is not None:
+            self._spinor(x0, "x0", like=b)
             x = x0.clone()
             p.x0_given = 1
         else:
@@ -172,6 +191,7 @@ class Lattice:
         nrhs = self._spinor(b, "b")
         p = _params(params, kw)
         if x0 is not None:
+            self._spinor(x0, "x0", like=b)
             x = x0.clone()
             p.x0_given = 1
         else:
@@ -188,7 +208,7 @@ class Lattice:
     def link_grad(self, Y, X, coef=1.0, stream=None):
         """G with d(sum Re<Y, D X>) = Re sum tr(G^dag dU), times coef (torch gradient convention)."""
         nrhs = self._spinor(X, "X")
-        self._spinor(Y, "Y")
+        self._spinor(Y, "Y", like=X)
         torch = _torch()
         G = torch.empty_like(self._U)
         _lib.check(_lib.load().wc_link_grad(self._ctx, _ptr(G), _ptr(Y), _ptr(X), nrhs, float(coef),
@@ -196,8 +216,10 @@ class Lattice:
         return G
 
     def force(self, phi, params: SolverParams | None = None, stream=None, **kw):
-        """Pseudofermion force of S = phi^dag (D^dag D)^-1 phi; returns (F, Y, X, stats)."""
-        self._spinor(phi, "phi")
+        """Pseudofermion force of S = phi^dag (D^dag D)^-1 phi for one pseudofermion field
+        phi [L0..L3][4][3]; returns (F, Y, X, stats)."""
+        if self._spinor(phi, "phi") != 1 or phi.dim() != 6:
+            raise WCError(-1, f"phi must be one field [L0..L3][4][3], got {tuple(phi.shape)}")
         torch = _torch()
         p = _params(params, kw)
         F = torch.empty_like(self._U)

@@ -154,3 +154,36 @@ def test_dirac_site_scales_span_wide_ranges(prec):
             m = np.maximum(m, np.roll(s, d, axis=1 + mu))
     err = np.linalg.norm(got - want, axis=(-2, -1))
     assert np.all(err <= 4 * TOL[prec] * m)
+
+
+def test_binding_checks_tensor_arguments():
+    """The Python binding rejects, before the library sees a pointer, tensors the kernels
+    would index out of bounds: an output or initial guess of another shape, an output that
+    overlaps the input, Y and X of different right-hand-side counts, more than one
+    pseudofermion field, and spinors of the wrong rank."""
+    import torch
+    import paper_1109_4279_amd as wc
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    lat = lattice(dims, block)
+    x = to_dev(synth.gaussian_spinor(dims, nrhs=2, seed=3))
+    one = x[0].contiguous()
+    with pytest.raises(wc.WCError, match="out has shape"):
+        lat.apply_D(x, out=lat.new_spinor(1))
+    with pytest.raises(wc.WCError, match="overlaps"):
+        lat.apply_D(x, out=x)
+    with pytest.raises(wc.WCError, match="x0 has shape"):
+        lat.solve(x, x0=one)
+    with pytest.raises(wc.WCError, match="x0 has shape"):
+        lat.solve_fgmres_dr(one, k=2, x0=x)
+    with pytest.raises(wc.WCError, match="Y has shape"):
+        lat.link_grad(one, x)
+    with pytest.raises(wc.WCError, match="phi must be one field"):
+        lat.force(x)
+    with pytest.raises(wc.WCError, match="must be"):
+        lat.apply_D(x.reshape((1,) + tuple(x.shape)))
+    with pytest.raises(wc.WCError, match="complex128"):
+        lat.apply_D(x.to(torch.complex64))
+    # a valid caller-provided output is used as given
+    out = lat.new_spinor(2)
+    assert lat.apply_D(x, out=out) is out
+    assert np.array_equal(to_np(out), to_np(lat.apply_D(x)))
