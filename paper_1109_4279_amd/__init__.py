@@ -85,6 +85,8 @@ class Lattice:
     def __init__(self, U, block=(4, 4, 4, 4), m0: float = 0.0, csw: float = 1.0, bc_t: int = 1, stream=None):
         lib = _lib.load()
         _need(U, "U", (3, 3))
+        if U.dim() != 7 or U.shape[0] != 4:
+            raise WCError(-1, f"U must be [4][L0][L1][L2][L3][3][3], got {tuple(U.shape)}")
         self.dims = tuple(int(d) for d in U.shape[1:5])
         self.block = tuple(int(b) for b in block)
         self.m0, self.csw, self.bc_t = float(m0), float(csw), int(bc_t)
@@ -267,6 +269,8 @@ def solve_batch(lattices, bs, params: SolverParams | None = None, stream=None, c
     bs[i] is a complex128 [nrhs_i][dims_i][4][3] tensor.  Returns (xs, stats)."""
     lib = _lib.load()
     n = len(lattices)
+    if len(bs) != n:
+        raise WCError(-1, f"{len(bs)} source tensors for {n} lattices")
     p = _params(params, kw)
     p.x0_given = 0
     xs, nr = [], []

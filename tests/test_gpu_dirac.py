@@ -183,6 +183,11 @@ def test_binding_checks_tensor_arguments():
         lat.apply_D(x.reshape((1,) + tuple(x.shape)))
     with pytest.raises(wc.WCError, match="complex128"):
         lat.apply_D(x.to(torch.complex64))
+    U = to_dev(gauge(dims))
+    with pytest.raises(wc.WCError, match="U must be"):
+        wc.Lattice(U[:3].contiguous(), block=block)
+    with pytest.raises(wc.WCError, match="source tensors"):
+        wc.solve_batch([lat, lat], [x])
     # a valid caller-provided output is used as given
     out = lat.new_spinor(2)
     assert lat.apply_D(x, out=out) is out
