@@ -725,6 +725,7 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   require(p.sap_prec >= 0 && p.sap_prec <= 3, WC_ERR_ARG, "bad sap_prec");
   require(p.tol > 0 && p.maxit >= 1, WC_ERR_ARG, "tol must be > 0 and maxit >= 1");
   require(p.eo == 0 || p.eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
+  require(p.dagger == 0 || p.dagger == 1, WC_ERR_ARG, "dagger must be 0 or 1");
   SolveSetup s;
   s.nkv = p.nkv;
   s.ncy = p.ncy;

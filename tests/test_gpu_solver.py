@@ -198,3 +198,21 @@ def test_zero_source(k):
         assert not x[0].any()
         assert st[1]["status"] == 0
         assert _true_res(dims, m0, csw, x[1], b[1]) <= 1e-10
+
+
+def test_solver_parameter_errors():
+    """Every out-of-range solver parameter is an argument error (-1) raised before any work,
+    for FGCR and FGMRES-DR, and the context stays usable."""
+    import paper_1109_4279_amd as wc
+    dims, block = (4, 4, 4, 4), (2, 2, 2, 2)
+    lat = lattice(dims, block)
+    b = to_dev(synth.gaussian_spinor(dims, seed=46))
+    bad = [dict(nkv=0), dict(nkv=33), dict(ncy=0), dict(nmr=0), dict(sap_prec=4), dict(sap_prec=-1),
+           dict(tol=0.0), dict(tol=float("nan")), dict(maxit=0), dict(eo=2), dict(dagger=2)]
+    for kw in bad:
+        for solve in (lat.solve, lambda rhs, **k: lat.solve_fgmres_dr(rhs, k=0, **k)):
+            with pytest.raises(wc.WCError) as e:
+                solve(b, **kw)
+            assert e.value.code == -1, kw
+    x, st = lat.solve(b, tol=1e-10)
+    assert st[0]["status"] == 0 and _true_res(dims, -0.1, 1.0, to_np(x), to_np(b)) <= 1e-10
