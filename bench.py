@@ -271,9 +271,113 @@ def summarise_pmc(fetch_csv, write_csv, out_json):
     return rec
 
 
+# kernels of the profile report: (label, kernel, its figure in the bench record)
+REPORT_LOOPS = [
+    ("even/odd block solver `k_sap_eo<F32,1,cached>` (dominant kernel, 4 steps)", "k_sap_eo<1, 1, true>",
+     lambda b: b["roofline"]["launch_ms"]),
+    ("plain MR block solver `k_sap_mr<F32,1,cached,256>` (4 steps)", "k_sap_mr<1, 1, true, 256>",
+     lambda b: b["roofline"]["plain_mr_half_sweep_ms"]),
+    ("D_w FP64 `k_dirac<F64,1,staged>`", "k_dirac<0, 1, true>", lambda b: b["dirac"]["f64"]["ms"]),
+    ("D_w FP32 `k_dirac<F32,1>`", "k_dirac<1, 1, false>", lambda b: b["dirac"]["f32"]["ms"]),
+    ("D_w FP16 `k_dirac<F16,1>`", "k_dirac<2, 1, false>", lambda b: b["dirac"]["f16"]["ms"]),
+    ("D_w BF16 `k_dirac<BF16,1>`", "k_dirac<3, 1, false>", lambda b: b["dirac"]["bf16"]["ms"]),
+]
+# kernels of the traffic table: (kernel, note, algorithmic read bytes per site)
+REPORT_TRAFFIC = [
+    ("k_sap_eo<1, 1, true>", "(one colour)", "864 per solved site = 432 per site"),
+    ("k_sap_mr<1, 1, true, 256>", "(one colour)", "864 per solved site = 432 per site"),
+    ("k_sap_eo<0, 1, false>", "(FP64, operator reloaded every phase)", "864 per site"),
+    ("k_dirac<0, 1, true>", "(FP64, tile staged in LDS)", "1344"),
+    ("k_dirac<1, 1, false>", "", "672"),
+    ("k_dirac<2, 1, false>", "", "352"),
+    ("k_dirac<3, 1, false>", "", "352"),
+]
+
+
+def _last_json_line(path):
+    return json.loads([ln for ln in open(path).read().splitlines() if ln.startswith('{"metric"')][-1])
+
+
+def profile_report(stats_dir, profiled_out, bench_out, fetch_csv, write_csv, traffic_json, out_md):
+    """Markdown summary of one profiling pass of the 16^3 x 32 workload: the kernel
+    statistics of `rocprofv3 --kernel-trace --stats -d STATS_DIR -o run -- bench.py --profile`
+    (its stdout in PROFILED_OUT), the last-20-dispatch averages of the benchmark loops beside
+    what bench.py printed (profiled and unprofiled: BENCH_OUT), and the HBM traffic record
+    that `--summarise-pmc FETCH_CSV WRITE_CSV TRAFFIC_JSON` wrote."""
+    import csv
+
+    prof_cmd = "--profile --steps 2 --warmup 1"
+    stats = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))))
+    spans = {}
+    for r in csv.DictReader(open(os.path.join(stats_dir, "run_kernel_trace.csv"))):
+        spans.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+
+    def last20_us(kernel):
+        for name, v in spans.items():
+            if kernel in name:
+                v = sorted(v)[-20:]
+                return sum(e - s for s, e in v) / len(v) / 1e3
+        return float("nan")
+
+    pb, ub = _last_json_line(profiled_out), _last_json_line(bench_out)
+    tk = json.load(open(traffic_json))
+    V = 131072
+
+    def pmc_cmd(counter, path):
+        d, f = os.path.split(path)
+        return (f"rocprofv3 --pmc {counter} --output-format csv -d {d} -o {f.split('_counter_collection')[0]} "
+                f"-- python -u bench.py {prof_cmd}")
+
+    out = ["# rocprofv3 summary: bench workload (16^3x32 mixed-precision SAP-FGCR), MI355X\n",
+           "Kernel trace and statistics (durations in microseconds):\n",
+           f"```\nrocprofv3 --kernel-trace --stats --output-format csv -d {stats_dir} -o run -- python -u bench.py "
+           f"{prof_cmd}\n```",
+           "The run holds 1 warm-up + 2 timed mixed solves with the even/odd block solver, the FP64\n"
+           "solves with the even/odd and with the plain MR block solver, the mixed solve with the plain\n"
+           "MR block solver, the D_w timing loops (2 warm-up + 2 x 20 graph-captured launches per\n"
+           "precision) and the Schwarz half-sweep timing loops of both block solvers.  The solves'\n"
+           "half-sweeps include the lighter first and last variants (no border update, no stores), so\n"
+           "the all-dispatch average of a block solver is below its benchmark-loop figure.\n",
+           "| kernel | calls | average | % of GPU time |\n|---|---|---|---|"]
+    for r in stats[:14]:
+        out.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    out += ["\nBenchmark-loop dispatches (last 20 of each kernel = the graph replay timed by `bench.py` with\n"
+            "HIP events on the launch stream):\n",
+            "| kernel | rocprofv3 avg (us) | bench.py (us) |\n|---|---|---|"]
+    unprof = []
+    for label, kernel, ms in REPORT_LOOPS:
+        out.append(f"| {label} | {last20_us(kernel):.2f} | {ms(pb) * 1e3:.2f} |")
+        unprof.append(f"{ms(ub) * 1e3:.2f}")
+    out.append(f"\n(`bench.py` column: what the same profiled command printed; the unprofiled `python bench.py`\n"
+               f"run printed {', '.join(unprof[:-1])} and {unprof[-1]} us.)\n\n"
+               f"HBM traffic of the same dispatches from two counter runs (FETCH_SIZE, then WRITE_SIZE),\n"
+               f"scaled by what the counters read for the run's 1 GiB device copy (fetch x {tk['fetch_scale']:.1f}, "
+               f"write x {tk['write_scale']:.1f};\nthe exact factors are in `{os.path.basename(traffic_json)}`); "
+               f"per launch and per lattice site (V = {V}):\n\n```\n{pmc_cmd('FETCH_SIZE', fetch_csv)}\n"
+               f"{pmc_cmd('WRITE_SIZE', write_csv)}\npython bench.py --summarise-pmc {fetch_csv} {write_csv} "
+               f"{traffic_json}\n```\n")
+    out.append("| kernel | fetch B/site | write B/site | algorithmic read B/site |\n|---|---|---|---|")
+    for kernel, note, alg in REPORT_TRAFFIC:
+        v = tk["kernels"].get(kernel)
+        if v is None:
+            continue
+        name = f"`{kernel}` {note}".rstrip()
+        out.append(f"| {name} | {v['fetch_bytes'] / V:.0f} | {v['write_bytes'] / V:.0f} | {alg} |")
+    out.append(f"\nThis summary: `python bench.py --profile-report {stats_dir} {profiled_out} {bench_out} {fetch_csv} "
+               f"{write_csv} {traffic_json} {out_md}`, where `{profiled_out}` holds the stdout of the kernel-trace "
+               f"run and `{bench_out}` that of `python bench.py`.")
+    open(out_md, "w").write("\n".join(out) + "\n")
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
         summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--profile-report":
+        if len(sys.argv) != 9:
+            sys.exit("usage: bench.py --profile-report STATS_DIR PROFILED_OUT BENCH_OUT FETCH_CSV WRITE_CSV "
+                     "TRAFFIC_JSON OUT_MD")
+        profile_report(*sys.argv[2:9])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -81,3 +81,39 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_profile_report(tmp_path):
+    """The profile summary: kernel statistics, last-20-dispatch averages beside the bench
+    figures, the traffic table per site, and every command that made it."""
+    stats = tmp_path / "stats"
+    stats.mkdir()
+    k = "void wc::k_sap_eo<1, 1, true>(wc::SapLaunch)"
+    with open(stats / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": k, "Calls": 25, "AverageNs": 50000.0, "Percentage": 70.0})
+    with open(stats / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for i in range(25):  # 5 warm-up dispatches of 90 us, then 20 of 47 us
+            w.writerow({"Kernel_Name": k, "Start_Timestamp": i * 10 ** 6,
+                        "End_Timestamp": i * 10 ** 6 + (90000 if i < 5 else 47000)})
+    rec = {"metric": "m", "roofline": {"launch_ms": 0.0475, "plain_mr_half_sweep_ms": 0.036},
+           "dirac": {p: {"ms": 0.02} for p in ("f64", "f32", "f16", "bf16")}}
+    (tmp_path / "prof.log").write_text("noise\n" + json.dumps(rec) + "\n")
+    (tmp_path / "bench.json").write_text(json.dumps(rec) + "\n")
+    traffic = {"fetch_scale": 2.0, "write_scale": 1.0,
+               "kernels": {"k_sap_eo<1, 1, true>": {"fetch_bytes": 131072 * 638.0, "write_bytes": 131072 * 144.0}}}
+    (tmp_path / "t.json").write_text(json.dumps(traffic))
+    out = tmp_path / "r.md"
+    bench.profile_report(str(stats), str(tmp_path / "prof.log"), str(tmp_path / "bench.json"),
+                         "pf/f_counter_collection.csv", "pw/w_counter_collection.csv", str(tmp_path / "t.json"),
+                         str(out))
+    md = out.read_text()
+    assert f"| `{k}` | 25 | 50.00 | 70.0 |" in md
+    assert "(dominant kernel, 4 steps) | 47.00 | 47.50 |" in md
+    assert "| `k_sap_eo<1, 1, true>` (one colour) | 638 | 144 |" in md
+    assert "rocprofv3 --pmc FETCH_SIZE --output-format csv -d pf -o f -- python -u bench.py --profile" in md
+    assert "rocprofv3 --pmc WRITE_SIZE --output-format csv -d pw -o w -- " in md
+    assert f"python bench.py --profile-report {stats} " in md
