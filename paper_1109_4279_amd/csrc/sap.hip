@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
           }
         }
       }
-      double sums[3 * NR];
+      R part[3 * NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         R qr_re = 0, qr_im = 0, qq = 0;
@@ -195,12 +195,13 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
             qr_im += qv.re * rv.im - qv.im * rv.re;
             qq += qv.re * qv.re + qv.im * qv.im;
           }
-        sums[3 * r] = qr_re;
-        sums[3 * r + 1] = qr_im;
-        sums[3 * r + 2] = qq;
+        part[3 * r] = qr_re;
+        part[3 * r + 1] = qr_im;
+        part[3 * r + 2] = qq;
       }
       // the LDS exchange of this step put a barrier after the previous reduction's reads
-      block_sum<3 * NR, false>(sums, red);
+      double sums[3 * NR];
+      block_sum_in<3 * NR, false>(part, sums, red);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double qq = sums[3 * r + 2];

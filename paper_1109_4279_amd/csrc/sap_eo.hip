@@ -354,7 +354,7 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
       cplx<R> q[NR][6];
       pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, sg, R(0.5), q);
       clover_half<P, NR, CACHE, true>(L, g, xe, s, re, q);
-      double sums[3 * NR];
+      R part[3 * NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         R qr_re = 0, qr_im = 0, qq = 0;
@@ -367,12 +367,13 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
             qq += qv.re * qv.re + qv.im * qv.im;
           }
         }
-        sums[3 * r] = qr_re;
-        sums[3 * r + 1] = qr_im;
-        sums[3 * r + 2] = qq;
+        part[3 * r] = qr_re;
+        part[3 * r + 1] = qr_im;
+        part[3 * r + 2] = qq;
       }
       // the LDS exchange of this step put a barrier after the previous reduction's reads
-      block_sum<3 * NR, false>(sums, red);
+      double sums[3 * NR];
+      block_sum_in<3 * NR, false>(part, sums, red);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double qq = sums[3 * r + 2];

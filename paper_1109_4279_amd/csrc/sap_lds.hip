@@ -185,7 +185,7 @@ __global__ __launch_bounds__(NR * 256) void k_sap_mr_lds(SapLaunch a) {
           qr_im += qv.re * rv.im - qv.im * rv.re;
           qq += qv.re * qv.re + qv.im * qv.im;
         }
-      double sv[3] = {wave_sum(double(qr_re)), wave_sum(double(qr_im)), wave_sum(double(qq))};
+      double sv[3] = {double(wave_sum(qr_re)), double(wave_sum(qr_im)), double(wave_sum(qq))};
       const int wid = tid >> 6;
       if ((tid & 63) == 0) {
         red[wid * 3] = sv[0];

@@ -397,4 +397,26 @@ template <int N, bool GUARD = true> WC_D void block_sum(double* v, double* lds) 
   }
 }
 
+// block_sum of N values held in precision T, result in `out` (every thread): the tree
+// within each wavefront runs in T, so an FP32 kernel's partial sums cross lanes as single
+// 32-bit words (half the shuffles of a double tree), and the sum over the wavefronts runs in
+// double.  `lds` and GUARD as for block_sum.
+template <int N, bool GUARD = true, class T> WC_D void block_sum_in(const T* v, double* out, double* lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) out[i] = double(wave_sum(v[i]));
+  if (GUARD) __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[wid * N + i] = out[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += lds[w * N + i];
+    out[i] = s;
+  }
+}
+
 }  // namespace wc
