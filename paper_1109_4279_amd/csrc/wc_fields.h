@@ -376,6 +376,23 @@ template <class T> WC_D T wave_sum(T v) {
   return v;
 }
 
+template <int CTRL> WC_D float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+WC_D float read_lane(float v, int lane) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane)); }
+
+// FP32 wavefront sum without LDS-crossbar shuffles: within each 16-lane row by DPP (lane
+// i plus lane i^1, then i^2 by quad permutes; then i plus 7-i within 8 lanes, i plus 15-i
+// within 16), after which every lane of a row holds the row's sum; the four row sums are
+// read as uniform values and added in a fixed order.  Needs all 64 lanes active.
+template <> WC_D float wave_sum<float>(float v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Sum over the work-group of up to N values per thread; result valid in every thread.
 // `lds` needs (blockDim/64) * N doubles.  GUARD = false drops the barrier that protects
 // `lds` from the previous call's readers, for callers that pass a barrier in between.
