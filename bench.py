@@ -363,6 +363,34 @@ def profile_report(stats_dir, profiled_out, bench_out, fetch_csv, write_csv, tra
             continue
         name = f"`{kernel}` {note}".rstrip()
         out.append(f"| {name} | {v['fetch_bytes'] / V:.0f} | {v['write_bytes'] / V:.0f} | {alg} |")
+    # one timed mixed solve from the trace: solves open with the |b|^2 kernel; the first
+    # warm-up-free one that runs the FP32 even/odd block solver, up to its first idle gap
+    # above 2 ms
+    trace = sorted((s0, e0, n.split("(")[0].replace("void ", "").replace("wc::", ""))
+                   for n, v in spans.items() for s0, e0 in v)
+    starts = [i for i, t in enumerate(trace) if t[2] == "k_norm2"]
+    solves = []
+    for j, i0 in enumerate(starts):
+        seg = trace[i0:starts[j + 1] if j + 1 < len(starts) else len(trace)]
+        for q in range(1, len(seg)):
+            if seg[q][0] - seg[q - 1][1] > 2_000_000:
+                seg = seg[:q]
+                break
+        if any(t[2] == "k_sap_eo<1, 1, true>" for t in seg):
+            solves.append(seg)
+    if len(solves) >= 2:
+        seg = solves[1]
+        span = (seg[-1][1] - seg[0][0]) / 1e6
+        busy = sum(e0 - s0 for s0, e0, _ in seg) / 1e6
+        per = {}
+        for s0, e0, n in seg:
+            per[n] = per.get(n, 0.0) + (e0 - s0) / 1e6
+        out.append(f"\nOne timed mixed solve (the second with the FP32 even/odd block solver in the trace): "
+                   f"{len(seg)} kernels,\n{busy:.2f} ms of kernels in a {span:.2f} ms span (idle between kernels "
+                   f"{span - busy:.2f} ms, {100 * (span - busy) / span:.1f} %):\n")
+        out.append("| kernel | ms | % of kernel time |\n|---|---|---|")
+        for n, v in sorted(per.items(), key=lambda x: -x[1])[:8]:
+            out.append(f"| `{n}` | {v:.3f} | {100 * v / busy:.1f} |")
     out.append(f"\nThis summary: `python bench.py --profile-report {stats_dir} {profiled_out} {bench_out} {fetch_csv} "
                f"{write_csv} {traffic_json} {out_md}`, where `{profiled_out}` holds the stdout of the kernel-trace "
                f"run and `{bench_out}` that of `python bench.py`.")

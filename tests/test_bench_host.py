@@ -96,9 +96,17 @@ def test_profile_report(tmp_path):
     with open(stats / "run_kernel_trace.csv", "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
         w.writeheader()
-        for i in range(25):  # 5 warm-up dispatches of 90 us, then 20 of 47 us
-            w.writerow({"Kernel_Name": k, "Start_Timestamp": i * 10 ** 6,
-                        "End_Timestamp": i * 10 ** 6 + (90000 if i < 5 else 47000)})
+        # two solves (|b|^2, three half-sweeps, 1 us apart), then 5 warm-up dispatches of
+        # 90 us and 20 of 47 us of the timing loop
+        for t0 in (0, 50 * 10 ** 6):
+            w.writerow({"Kernel_Name": "wc::k_norm2(wc::VecLaunch)", "Start_Timestamp": t0,
+                        "End_Timestamp": t0 + 10000})
+            for j in range(3):
+                w.writerow({"Kernel_Name": k, "Start_Timestamp": t0 + 11000 + j * 48000,
+                            "End_Timestamp": t0 + 11000 + j * 48000 + 47000})
+        for i in range(25):
+            t0 = 100 * 10 ** 6 + i * 10 ** 6
+            w.writerow({"Kernel_Name": k, "Start_Timestamp": t0, "End_Timestamp": t0 + (90000 if i < 5 else 47000)})
     rec = {"metric": "m", "roofline": {"launch_ms": 0.0475, "plain_mr_half_sweep_ms": 0.036},
            "dirac": {p: {"ms": 0.02} for p in ("f64", "f32", "f16", "bf16")}}
     (tmp_path / "prof.log").write_text("noise\n" + json.dumps(rec) + "\n")
@@ -117,3 +125,6 @@ def test_profile_report(tmp_path):
     assert "rocprofv3 --pmc FETCH_SIZE --output-format csv -d pf -o f -- python -u bench.py --profile" in md
     assert "rocprofv3 --pmc WRITE_SIZE --output-format csv -d pw -o w -- " in md
     assert f"python bench.py --profile-report {stats} " in md
+    # the second solve: 4 kernels, 0.151 ms of kernels in a 0.154 ms span
+    assert "4 kernels,\n0.15 ms of kernels in a 0.15 ms span" in md
+    assert "| `k_sap_eo<1, 1, true>` | 0.141 |" in md
