@@ -111,3 +111,49 @@ def test_product_package_does_not_import_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", src, flags=re.M), f
                 assert "oracle/" not in src, f
+
+
+def test_header_is_c99_and_links(tmp_path):
+    """A C99 client (-Wall -Wextra -pedantic -Werror) that includes only wc.h, takes the
+    address of every declared entry point and links against libwc.so: the header is plain C
+    and the library resolves every symbol at link time.  Run, it checks the defaults and two
+    argument errors, which touch no device."""
+    import shutil
+    import subprocess
+    from paper_1109_4279_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwc.so not built")
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    refs = "\n".join(f"  (void (*)(void)){n}," for n in _declared())
+    src = tmp_path / "client.c"
+    src.write_text(f"""#include <stdio.h>
+#include <string.h>
+#include "wc.h"
+static void (*const entry_points[])(void) = {{
+{refs}
+}};
+int main(void) {{
+  wc_ctx* ctx = NULL;
+  const int dims[4] = {{4, 4, 4, 4}}, block[4] = {{2, 2, 2, 2}};
+  wc_solver_params p;
+  size_t i;
+  for (i = 0; i < sizeof entry_points / sizeof entry_points[0]; ++i)
+    if (!entry_points[i]) return 1;
+  wc_default_params(&p);
+  if (p.nkv != 16 || p.eo != 0 || p.dagger != 0) return 2;
+  if (wc_create_gauge(&ctx, dims, block, NULL, 1, NULL) != WC_ERR_ARG || strlen(wc_last_error()) == 0) return 3;
+  if (wc_fgcr_solve(NULL, NULL, NULL, 1, &p, NULL, NULL) != WC_ERR_ARG) return 4;
+  printf("%d\\n", wc_version());
+  return 0;
+}}
+""")
+    lib_dir = os.path.dirname(_lib.LIB_PATH)
+    exe = tmp_path / "client"
+    cc = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                         str(src), "-L", lib_dir, "-lwc", f"-Wl,-rpath,{lib_dir}", "-o", str(exe)],
+                        capture_output=True, text=True, timeout=120)
+    assert cc.returncode == 0, cc.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, (run.returncode, run.stderr)
+    assert run.stdout.strip() == "100"
