@@ -98,6 +98,7 @@ template <class R, bool CACHE> struct LaneSite {
   Herm6<R> C[CACHE ? 1 : 1];  // clover block s (scaled) when cached
 };
 
+// the geometry part of LaneSite (lane_links adds the cached links)
 template <int P, class R, bool CACHE>
 WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const int* lc, int s, const short* slot,
                     LaneSite<R, CACHE>& x) {
@@ -115,11 +116,16 @@ WC_D void lane_site(const LatDesc& L, const Geom& g, int site, int local, const 
     x.snf[j] = gld_s16(slot, x.lnf[j]);
     x.snb[j] = gld_s16(slot, x.lnb[j]);
   }
+}
+
+// the cached operator's links of lane_site's site (CACHE only)
+template <int P, class R, bool CACHE>
+WC_D void lane_links(const LatDesc& L, const Geom& g, int s, LaneSite<R, CACHE>& x) {
   if (CACHE) {
-    const int base = site - local;
+    const int base = x.site - x.local;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      x.Uf[CACHE ? j : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, 2 * s + j, site);
+      x.Uf[CACHE ? j : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, 2 * s + j, x.site);
       x.Ub[CACHE ? j : 0] = LinkIO<P>::load(L.gauge, L.gscale, g.V, 2 * s + j, base + x.lnb[j]);
     }
   }
@@ -275,10 +281,6 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     const int ls = 2 * nh;  // LDS row: slots 0..nh-1 even sites, nh..2nh-1 odd sites, in pair order
     lane_site<P, R, CACHE>(L, g, base + lel, lel, lce, s, slot, xe);
     lane_site<P, R, CACHE>(L, g, base + lol, lol, lco, s, slot, xo);
-    if (CACHE) {
-      xe.C[0] = clover_block_scaled<P, R>(L, g.V, xe.site, s);
-      xo.C[0] = clover_block_scaled<P, R>(L, g.V, xo.site, s);
-    }
 
     FieldRef frho[NR], fz[NR], fpsi[NR];
     const int sb = spinor_site_bytes(P);
@@ -321,6 +323,14 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
         }
     }
 
+    // the cached operator is loaded after the residual and the border update, whose loads
+    // the first arithmetic waits for
+    lane_links<P, R, CACHE>(L, g, s, xe);
+    lane_links<P, R, CACHE>(L, g, s, xo);
+    if (CACHE) {
+      xe.C[0] = clover_block_scaled<P, R>(L, g.V, xe.site, s);
+      xo.C[0] = clover_block_scaled<P, R>(L, g.V, xo.site, s);
+    }
     // t_o = A_oo^-1 eta_o ; source of the Schur system: eta_e - H_eo t_o
     cplx<R> to[NR][6];
     clover_half<P, NR, CACHE, false>(L, g, xo, s, eo, to);
