@@ -455,7 +455,8 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   a.skip = skip;
   a.dagger = dagger;
   a.block = block;
-  a.stage = dirac_stage_mode(B, prec);
+  // a tile of nr rhs that does not fit a work-group's LDS runs unstaged
+  a.stage = dirac_stage_mode(B, prec) && dirac_stage_lds_bytes(prec, nr) <= LDS_MAX_BYTES;
   launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
 }
 

@@ -193,10 +193,16 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
   }
 }
 
+// dynamic LDS of a staged launch: the tile's input spinors (12 complex) and site scale per
+// rhs of the lane's tile (nr clamped to the 1..4 the launch switch instantiates)
+size_t dirac_stage_lds_bytes(int prec, int nr) {
+  const size_t real = prec == P_F64 ? 8 : 4;
+  return (2 * real * 12 + real) * (size_t)std::min(std::max(nr, 1), 4) * WG;
+}
+
 template <int P, bool S>
 static void launch_ps(const DiracLaunch& a, int nr, int grid, hipStream_t st) {
-  typedef typename Real<P>::T R;
-  auto lds = [&](int n) { return S ? (sizeof(cplx<R>) * 12 + sizeof(R)) * n * WG : 0; };
+  auto lds = [&](int n) { return S ? dirac_stage_lds_bytes(P, n) : size_t(0); };
   switch (nr) {
     case 1: hipLaunchKernelGGL((k_dirac<P, 1, S>), dim3(grid), dim3(WG), lds(1), st, a); break;
     case 2: hipLaunchKernelGGL((k_dirac<P, 2, S>), dim3(grid), dim3(WG), lds(2), st, a); break;

@@ -26,6 +26,8 @@ struct DiracLaunch {
   int stage;           // every lattice has 256-site tiles: stage each tile's input in LDS
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
+size_t dirac_stage_lds_bytes(int prec, int nr);  // dynamic LDS of a staged D_w launch
+constexpr size_t LDS_MAX_BYTES = 160 * 1024;       // LDS a gfx950 work-group may allocate
 
 // ----------------------------------------------------------------- Schwarz block MR
 struct SapLaunch {

@@ -82,3 +82,21 @@ def test_rhs_tile_autotuner_keeps_solutions():
     U, A = gauge(dims), clover(dims, M0, CSW)
     for r in (2, 9):
         assert _true_res(U, A, x1[r], b[r]) <= 1e-10
+
+
+def test_fp64_dirac_tile_beyond_the_lds_stage():
+    """FP64 D_w with 4 rhs per lane on 4^4 tiles: staging the tile's input would take 200 KB
+    of LDS, more than a work-group may hold, so that tile runs unstaged.  The FP64 rhs-tile
+    autotuner (which tries 1, 2 and 4 rhs per lane) and an FP64 solve with nr_dirac = 4
+    both run, and the solve reaches 1e-10."""
+    dims, block = (16, 8, 8, 8), (4, 4, 4, 4)
+    lat = lattice(dims, block, M0, CSW)
+    b = synth.gaussian_spinor(dims, nrhs=4, seed=61)
+    nd, ns = lat.autotune(4, prec="f64")
+    assert nd in (1, 2, 4) and ns == 1
+    x, st = lat.solve(to_dev(b), nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec="f64", nr_dirac=4)
+    assert all(s["status"] == 0 for s in st)
+    U, A = gauge(dims), clover(dims, M0, CSW)
+    x = to_np(x)
+    for r in (0, 3):
+        assert _true_res(U, A, x[r], b[r]) <= 1e-10
