@@ -35,24 +35,24 @@ namespace wc {
 constexpr int EO_MAX_WAVES = 4;  // blocks of at most 256 sites: 128 pairs, 256 lanes
 
 // acc += w * (1 + SGN gamma_mu)-hop of the transported neighbour spinor p, for mu = 2s + J.
-// J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.  sg = +1 for s = 0, -1 for s = 1.
+// J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.
 template <class R, int J, int SGN, bool DAG>
-WC_D void hop_dir(const SU3<R>& U, const Spinor<R>& p, int s, R sg, R w, Spinor<R>& acc) {
+WC_D void hop_dir(const SU3<R>& U, const Spinor<R>& p, int s, R w, Spinor<R>& acc) {
   Half<R> h;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const cplx<R> u0 = p.c[0][a], u1 = p.c[1][a], l0 = p.c[2][a], l1 = p.c[3][a];
     // J = 0: mu = 0: h = u - SGN (l0, l1);        mu = 2: h = u - SGN (l1, -l0)
     // J = 1: mu = 1: h = u - SGN i (l1, l0);      mu = 3: h = u - SGN i (l0, -l1)
+    // the lane sign (+1 for s = 0, -1 for s = 1) enters as a negated select
     cplx<R> x0, x1;
     if (J == 0) {
       x0 = s ? l1 : l0;
-      x1 = s ? l0 : l1;
+      x1 = s ? -l0 : l1;
     } else {
       x0 = s ? l0 : l1;
-      x1 = s ? l1 : l0;
+      x1 = s ? -l1 : l0;
     }
-    x1 = sg * x1;
     if (J == 0) {
       h.c[0][a] = SGN > 0 ? u0 - x0 : u0 + x0;
       h.c[1][a] = SGN > 0 ? u1 - x1 : u1 + x1;
@@ -71,15 +71,13 @@ WC_D void hop_dir(const SU3<R>& U, const Spinor<R>& p, int s, R sg, R w, Spinor<
     // J = 1: mu = 1: lower += SGN i (t1, t0);     mu = 3: lower += SGN i (t0, -t1)
     cplx<R> y0, y1;
     if (J == 0) {
-      y0 = s ? t1 : t0;
+      y0 = s ? -t1 : t0;
       y1 = s ? t0 : t1;
-      y0 = sg * y0;
       acc.c[2][a] = SGN > 0 ? acc.c[2][a] - y0 : acc.c[2][a] + y0;
       acc.c[3][a] = SGN > 0 ? acc.c[3][a] - y1 : acc.c[3][a] + y1;
     } else {
       y0 = s ? t0 : t1;
-      y1 = s ? t1 : t0;
-      y1 = sg * y1;
+      y1 = s ? -t1 : t0;
       acc.c[2][a] = SGN > 0 ? acc.c[2][a] + timesI(y0) : acc.c[2][a] - timesI(y0);
       acc.c[3][a] = SGN > 0 ? acc.c[3][a] + timesI(y1) : acc.c[3][a] - timesI(y1);
     }
@@ -141,7 +139,7 @@ WC_D void lds_spinor(const cplx<R>* lds, int ls, int r, int slot, Spinor<R>& p) 
 // LDS.  Every lane of the wavefront must call this (it shuffles).
 template <int P, int NR, bool CACHE, class R>
 WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x, bool act, const cplx<R>* lds,
-                    int ls, int s, R sg, R wt, cplx<R> (*out)[6]) {
+                    int ls, int s, R wt, cplx<R> (*out)[6]) {
   Spinor<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) zero(acc[r]);
@@ -157,7 +155,7 @@ WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x
         for (int r = 0; r < NR; ++r) {
           Spinor<R> p;
           lds_spinor<NR>(lds, ls, r, x.snf[J], p);
-          hop_dir<R, J, -1, false>(U, p, s, sg, w, acc[r]);
+          hop_dir<R, J, -1, false>(U, p, s, w, acc[r]);
         }
       }
       if (x.b[J]) {
@@ -168,7 +166,7 @@ WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x
         for (int r = 0; r < NR; ++r) {
           Spinor<R> p;
           lds_spinor<NR>(lds, ls, r, x.snb[J], p);
-          hop_dir<R, J, +1, true>(U, p, s, sg, w, acc[r]);
+          hop_dir<R, J, +1, true>(U, p, s, w, acc[r]);
         }
       }
     };
@@ -251,7 +249,6 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
   cplx<R>* lds = (cplx<R>*)(smem_d + EO_MAX_WAVES * 3 * NR);  // [NR][12][bvol]
 
   const int s = threadIdx.x & 1;
-  const R sg = s ? R(-1) : R(1);
   const int pr = threadIdx.x >> 1;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     const WorkItem w = a.items[xcd_remap(it0, a.nitems)];
@@ -338,7 +335,7 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     __syncthreads();
     {
       cplx<R> d[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, sg, R(0.5), d);
+      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, R(0.5), d);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -356,13 +353,13 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
       __syncthreads();
       {
         cplx<R> t[NR][6], wo[NR][6];
-        pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, sg, R(-0.5), t);
+        pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, R(-0.5), t);
         clover_half<P, NR, CACHE, false>(L, g, xo, s, t, wo);
         if (ho) half_to_lds<NR>(lds, ls, nh + pr, s, wo);
       }
       __syncthreads();
       cplx<R> q[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, sg, R(0.5), q);
+      pair_hops<P, NR, CACHE>(L, g, xe, he, lds, ls, s, R(0.5), q);
       clover_half<P, NR, CACHE, true>(L, g, xe, s, re, q);
       R part[3 * NR];
 #pragma unroll
@@ -404,7 +401,7 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
     cplx<R> zo[NR][6];
     {
       cplx<R> t[NR][6];
-      pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, sg, R(0.5), t);
+      pair_hops<P, NR, CACHE>(L, g, xo, ho, lds, ls, s, R(0.5), t);
       clover_half<P, NR, CACHE, false>(L, g, xo, s, t, zo);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
