@@ -51,7 +51,7 @@ typedef enum {
   WC_ERR_GEOMETRY = -2,      /* lattice / block shape not allowed (see above) */
   WC_ERR_HIP = -3,           /* HIP runtime error; message kept */
   WC_ERR_OOM = -4,           /* device allocation failed */
-  WC_ERR_NOT_CONVERGED = -5, /* solve stopped at maxit; x and stats are written */
+  WC_ERR_NOT_CONVERGED = -5, /* solve stopped at maxit or stagnated; x and stats written */
   WC_ERR_BREAKDOWN = -6,     /* NaN/Inf or a vanishing Krylov direction; x and stats written */
   WC_ERR_STATE = -7          /* clover term not created yet */
 } wc_status;
@@ -76,7 +76,14 @@ typedef struct {
   int nr_sap;    /* right-hand sides per work-group in the block solver (0: library choice) */
   int eo;        /* 1: even/odd-preconditioned block solver (Sec. 4, Table 1), 0: MR on D_Lambda */
   int dagger;    /* 1: solve D^dag x = b, as g5 D^-1 g5 (gamma5-hermiticity of D); 0: D x = b */
+  int stag;      /* stagnation test (Sec. 4: restarts): a right-hand side whose FP64 true
+                    residual has not dropped over `stag` restarts in a row stops with
+                    WC_ERR_NOT_CONVERGED (x and stats written); 0 switches the test off */
+  int timing;    /* 1: run the FGCR restart cycles eagerly with HIP events between the
+                    phases and report t_sap/t_dirac/t_blas (slower; FGCR only) */
 } wc_solver_params;
+
+#define WC_HIST_MAX 64 /* restarts whose true residual wc_solver_stats keeps */
 
 typedef struct {
   int status;          /* wc_status of this right-hand side */
@@ -85,11 +92,38 @@ typedef struct {
   int breakdown;       /* 1 if the recursion broke down (NaN/Inf or zero direction) */
   double rel_true_res; /* last FP64 ||b - D x|| / ||b|| */
   double time_ms;      /* solve time of the whole call (same for every rhs of a call) */
+  int reorth;          /* FGCR directions that took a second Gram-Schmidt pass */
+  int stagnated;       /* 1 if the stagnation test stopped this right-hand side */
+  int nhist;           /* entries of res_hist: min(restarts, WC_HIST_MAX) */
+  int timed;           /* 1 if the phase times below were measured (params.timing) */
+  double t_setup_ms;   /* whole call, stream time: |b|, initial residual */
+  double t_cycles_ms;  /* whole call, stream time: the restart cycles */
+  double t_finish_ms;  /* reserved (0) */
+  double t_sap_ms;     /* with timing: Schwarz preconditioner incl. conversions */
+  double t_dirac_ms;   /* with timing: FP64 D (chi = D phi and the true residuals) */
+  double t_blas_ms;    /* with timing: Gram-Schmidt, reductions, solution update */
+  double res_hist[WC_HIST_MAX]; /* relative FP64 true residual after restart 1, 2, ... */
 } wc_solver_stats;
 
 /* Fill p with the library defaults: nkv 16, ncy 5, nmr 4, sap_prec WC_F32, tol 1e-10,
- * maxit 10000, no initial guess, graphs on, automatic RHS tiles, MR block solver, D x = b. */
+ * maxit 10000, no initial guess, graphs on, automatic RHS tiles, MR block solver, D x = b,
+ * stagnation test over 3 restarts, no phase timing. */
 void wc_default_params(wc_solver_params* p);
+
+/* Per-context kernel choices (a batched call uses those of its first context).
+ * WC_OPT_SAP_CACHE    -1 automatic (default): the block solver keeps the block operator in
+ *                     registers when a launch has at most two work items per CU;
+ *                     0 reload it in every phase; 1 keep it in registers (FP32-math kernels).
+ * WC_OPT_DIRAC_STAGE  -1 automatic (default): FP64 D_w stages each 256-site tile's input
+ *                     in LDS; 0 never; 1 also for FP32 and 16-bit storage.
+ * Both select kernels only; results agree to rounding.  Errors: WC_ERR_ARG. */
+typedef enum { WC_OPT_SAP_CACHE = 0, WC_OPT_DIRAC_STAGE = 1 } wc_option;
+int wc_set_option(wc_ctx* ctx, int option, int value);
+
+/* Right-hand sides handled together, per storage precision prec: nr_dirac per lane of D
+ * (1..4), nr_sap per work-group of the plain block solver and nr_sap_eo of the even/odd one
+ * (1..2; FP64 1).  0 leaves the library's choice (or the autotuner's).  Errors: WC_ERR_ARG. */
+int wc_set_tiles(wc_ctx* ctx, int prec, int nr_dirac, int nr_sap, int nr_sap_eo);
 
 /* Create a context for one lattice: copies the gauge field U (device, complex128, see
  * above) and lays it out block-major with Schwarz blocks block[4] (Sec. 5: points of one
@@ -173,6 +207,17 @@ int wc_fgmres_dr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, cons
  * (product rule over the plaquette leaves).  Used for the backward of D and of D^-1. */
 int wc_link_grad(wc_ctx* ctx, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream);
 
+/* The pseudofermion action S = phi^dag (D^dag D)^-1 phi = ||Y||^2 (Sec. 1: the HMC action of
+ * the fermion determinant): Y = D^-dag phi and X = D^-1 Y by two solves with p (complex128
+ * spinors, caller-owned, written), *S (host) = ||Y||^2 summed on the device in FP64.  st
+ * (may be NULL) gets 2 entries.  Errors as wc_fgcr_solve; Y, X, S are written regardless. */
+int wc_pseudofermion_action(wc_ctx* ctx, const void* phi, const wc_solver_params* p, double* S, void* Y, void* X,
+                            wc_solver_stats* st, void* stream);
+
+/* out = coef * in for nrhs complex128 spinor fields of the context's lattice (the action's
+ * derivative with respect to phi is 2 X).  out may equal in. */
+int wc_spinor_scale(wc_ctx* ctx, void* out, const void* in, int nrhs, double coef, void* stream);
+
 /* Harmonic Ritz pairs of an Arnoldi cycle (Sec. 4, the deflated restarts of FGMRES-DR),
  * computed on the host in FP64: eigenpairs of H + |h_{m+1,m}|^2 H^-H e_m e_m^T with H the
  * top m x m block of the (m+1) x m matrix Hbar.  Hbar: host complex128, column-major with
@@ -189,9 +234,11 @@ int wc_harmonic_ritz(int m, const void* Hbar, void* theta, void* G);
 int wc_force(wc_ctx* ctx, void* F, const void* phi, const wc_solver_params* p, wc_solver_stats* st, void* Y,
              void* X, void* stream);
 
-/* Autotune: time the RHS tile of D and of both block solvers for (nrhs, prec) and keep the
- * fastest in the context; nr_out[0..1] receive the chosen (D, plain block solver) tiles. */
-int wc_autotune(wc_ctx* ctx, int nrhs, int prec, int nr_out[2], void* stream);
+/* Autotune for solves of nrhs right-hand sides whose preconditioner runs in prec: time the
+ * RHS tile of D in prec, of the FP64 D of the outer solver and of both block solvers in
+ * prec, and keep the fastest in the context.  nr_out[0..3] receive the chosen tiles:
+ * D in prec, FP64 D, plain block solver, even/odd block solver. */
+int wc_autotune(wc_ctx* ctx, int nrhs, int prec, int nr_out[4], void* stream);
 
 /* Choose the Schwarz block shape of the context among the valid shapes with at most 256
  * sites by timing a short solve (tolerance p->tol) of one Gaussian source for each;
@@ -210,7 +257,7 @@ void wc_destroy(wc_ctx* ctx);
 /* Message of the last error on this thread (static storage, valid until the next call). */
 const char* wc_last_error(void);
 
-/* Interface version: 100 * major + minor. */
+/* Interface version: 100 * major + minor (2.0). */
 int wc_version(void);
 
 #ifdef __cplusplus

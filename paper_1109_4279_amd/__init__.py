@@ -233,9 +233,43 @@ class Lattice:
         return F, Y, X, [s.as_dict() for s in st]
 
     def autotune(self, nrhs, prec="f32", stream=None):
-        out = (ctypes.c_int * 2)()
+        """Tune the rhs tiles for solves of nrhs rhs whose preconditioner runs in prec.
+        Returns (D tile in prec, FP64 D tile, plain block-solver tile, even/odd tile)."""
+        out = (ctypes.c_int * 4)()
         _lib.check(_lib.load().wc_autotune(self._ctx, int(nrhs), PREC[prec], out, _stream(stream)))
-        return int(out[0]), int(out[1])
+        return tuple(int(v) for v in out)
+
+    def set_option(self, name, value):
+        """Kernel choice of this context: "sap_cache" or "dirac_stage", -1 (automatic), 0 or 1."""
+        _lib.check(_lib.load().wc_set_option(self._ctx, _lib.OPTIONS[name], int(value)))
+
+    def set_tiles(self, prec, nr_dirac=0, nr_sap=0, nr_sap_eo=0):
+        """Right-hand sides handled together in precision prec (0: the library's choice)."""
+        _lib.check(_lib.load().wc_set_tiles(self._ctx, PREC[prec], int(nr_dirac), int(nr_sap), int(nr_sap_eo)))
+
+    def action(self, phi, params: SolverParams | None = None, stream=None, **kw):
+        """Pseudofermion action S = phi^dag (D^dag D)^-1 phi = |Y|^2 for one field phi;
+        returns (S, Y, X, stats) with Y = D^-dag phi and X = D^-1 Y."""
+        if self._spinor(phi, "phi") != 1 or phi.dim() != 6:
+            raise WCError(-1, f"phi must be one field [L0..L3][4][3], got {tuple(phi.shape)}")
+        p = _params(params, kw)
+        Y = self.new_spinor()
+        X = self.new_spinor()
+        S = ctypes.c_double()
+        st = (SolverStats * 2)()
+        _lib.check(_lib.load().wc_pseudofermion_action(self._ctx, _ptr(phi), ctypes.byref(p), ctypes.byref(S),
+                                                       _ptr(Y), _ptr(X), st, _stream(stream)))
+        return S.value, Y, X, [s.as_dict() for s in st]
+
+    def scale(self, x, coef, out=None, stream=None):
+        """out = coef * x for spinor fields of this lattice."""
+        nrhs = self._spinor(x, "x")
+        if out is None:
+            out = self.new_spinor(None if x.dim() == 6 else nrhs)
+        else:
+            self._spinor(out, "out", like=x)
+        _lib.check(_lib.load().wc_spinor_scale(self._ctx, _ptr(out), _ptr(x), nrhs, float(coef), _stream(stream)))
+        return out
 
     def autotune_block(self, params: SolverParams | None = None, stream=None, **kw):
         p = _params(params, kw)

@@ -21,18 +21,28 @@ class SolverParams(ctypes.Structure):
         ("nkv", ctypes.c_int), ("ncy", ctypes.c_int), ("nmr", ctypes.c_int), ("sap_prec", ctypes.c_int),
         ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("x0_given", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("nr_dirac", ctypes.c_int), ("nr_sap", ctypes.c_int),
-        ("eo", ctypes.c_int), ("dagger", ctypes.c_int),
+        ("eo", ctypes.c_int), ("dagger", ctypes.c_int), ("stag", ctypes.c_int), ("timing", ctypes.c_int),
     ]
+
+
+HIST_MAX = 64
+OPTIONS = {"sap_cache": 0, "dirac_stage": 1}
 
 
 class SolverStats(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
         ("breakdown", ctypes.c_int), ("rel_true_res", ctypes.c_double), ("time_ms", ctypes.c_double),
+        ("reorth", ctypes.c_int), ("stagnated", ctypes.c_int), ("nhist", ctypes.c_int), ("timed", ctypes.c_int),
+        ("t_setup_ms", ctypes.c_double), ("t_cycles_ms", ctypes.c_double), ("t_finish_ms", ctypes.c_double),
+        ("t_sap_ms", ctypes.c_double), ("t_dirac_ms", ctypes.c_double), ("t_blas_ms", ctypes.c_double),
+        ("res_hist", ctypes.c_double * HIST_MAX),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "res_hist"}
+        d["res_hist"] = [self.res_hist[i] for i in range(self.nhist)]
+        return d
 
 
 class WCError(RuntimeError):
@@ -65,6 +75,11 @@ _SIGS = {
     "wc_link_grad": (_I, [_P, _P, _P, _P, _I, _D, _P]),
     "wc_force": (_I, [_P, _P, _P, ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), _P, _P, _P]),
     "wc_autotune": (_I, [_P, _I, _I, ctypes.POINTER(_I), _P]),
+    "wc_set_option": (_I, [_P, _I, _I]),
+    "wc_set_tiles": (_I, [_P, _I, _I, _I, _I]),
+    "wc_pseudofermion_action": (_I, [_P, _P, ctypes.POINTER(SolverParams), ctypes.POINTER(_D), _P, _P,
+                                     ctypes.POINTER(SolverStats), _P]),
+    "wc_spinor_scale": (_I, [_P, _P, _P, _I, _D, _P]),
     "wc_autotune_block": (_I, [_P, ctypes.POINTER(SolverParams), ctypes.POINTER(_I), _P]),
     "wc_bench_dirac": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_D), _P]),
     "wc_bench_sap": (_I, [_P, _I, _I, _I, _I, _I, ctypes.POINTER(_D), _P]),

@@ -1,8 +1,7 @@
 """torch.autograd.Functions around the library's operator, solve and pseudofermion action.
 
-Every application of D, D^dag, D^-1 and D^-dag and every link derivative runs in libwc;
-torch only forms the action's value |Y|^2 from the library's Y and scales X by 2 dS in
-its backward.  These classes route tensors:
+Every application of D, D^dag, D^-1 and D^-dag, the action's value, its derivatives and
+every link derivative run in libwc; these classes only route tensors:
 
 * ``dirac_apply(U, x)``  y = D[U] x;  backward: dx = D^dag dy = g5 D g5 dy,
   dU = link derivative of Re<dy, D x> (torch's conjugate-gradient convention).
@@ -80,13 +79,12 @@ class DiracSolve(torch.autograd.Function):
 class PseudofermionAction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U, phi, opts, params):
-        adj = _adjoint(params)
+        _adjoint(params)
         lat = _lattice(U, opts)
-        Y, _ = lat.solve(phi.detach().contiguous(), params=adj)  # Y = D^-dag phi
-        X, _ = lat.solve(Y, params=params)
+        S, Y, X, _ = lat.action(phi.detach().contiguous(), params=params)  # Y = D^-dag phi, X = D^-1 Y
         ctx.lat = lat
         ctx.save_for_backward(Y, X)
-        return torch.vdot(Y.flatten(), Y.flatten()).real
+        return torch.tensor(S, dtype=torch.float64, device=phi.device)
 
     @staticmethod
     def backward(ctx, gS):
@@ -94,7 +92,7 @@ class PseudofermionAction(torch.autograd.Function):
         lat = ctx.lat
         g = float(gS)
         gU = lat.link_grad(Y, X, coef=-2.0 * g) if ctx.needs_input_grad[0] else None
-        gphi = 2.0 * g * X if ctx.needs_input_grad[1] else None
+        gphi = lat.scale(X, 2.0 * g) if ctx.needs_input_grad[1] else None
         return gU, gphi, None, None
 
 

@@ -23,6 +23,9 @@ void launch_gamma5_canon(long long nsite, const void* src, void* dst, hipStream_
 void launch_gamma5_f64(void* f, long long V, int nrhs, hipStream_t st);
 void launch_clover_export(const Geom& g, const void* c64, void* out, hipStream_t st);
 void launch_fill_hash(long long n, unsigned seed, void* out, hipStream_t st);
+void launch_scale_canon(long long n, double coef, const void* in, void* out, hipStream_t st);
+void launch_norm2_canon(long long n, const void* v, double* work, hipStream_t st);
+static_assert(HIST_MAX == WC_HIST_MAX, "history length of the device state and the interface");
 
 struct Error {
   int code;
@@ -189,6 +192,8 @@ struct wc_ctx {
   int nr_dirac[4] = {0, 0, 0, 0};
   int nr_sap[4] = {0, 0, 0, 0};
   int nr_sap_eo[4] = {0, 0, 0, 0};
+  int opt_sap_cache = -1;    // WC_OPT_SAP_CACHE: -1 automatic, 0 reload, 1 registers
+  int opt_dirac_stage = -1;  // WC_OPT_DIRAC_STAGE: -1 automatic, 0 off, 1 on
   std::map<int, std::unique_ptr<wc::Batch>> batches;  // single-lattice batches by nrhs
   hipStream_t cap = nullptr;                           // capture stream for graphs
   ~wc_ctx();
@@ -262,6 +267,7 @@ struct Batch {
   DevBuf d_chi, d_phi;
   Field sap_rho, sap_z, sap_psi;
   DevBuf sys, skip;
+  DevBuf hist;  // [nsys][HIST_MAX] relative true residual after each restart
   // apply / bench buffers per precision
   Field ain[4], aout[4];
   // captured restart cycle
@@ -272,6 +278,7 @@ struct Batch {
   Field arn_vlast;
   DevBuf d_arn_v, arn;
   std::map<std::string, hipGraphExec_t> arn_graphs;
+  std::string arn_key;  // graph_key the graphs in arn_graphs were captured under
 
   ~Batch() {
     if (graph) (void)hipGraphExecDestroy(graph);
@@ -425,14 +432,11 @@ static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested, int e
 
 // Tile staging of the D_w input needs 256-site tiles in every lattice of the batch.  It
 // pays for FP64 (whose spinors overflow L2 between the nine reads of each) and costs for
-// FP32 / 16-bit (measured on MI355X); WC_DIRAC_STAGE=0/1 forces it off/on where allowed.
+// FP32 / 16-bit (measured on MI355X); the WC_OPT_DIRAC_STAGE option of the batch's first
+// context forces it off/on where allowed.
 static int dirac_stage_mode(const Batch& B, int prec) {
-  static int forced = -2;
-  if (forced == -2) {
-    const char* e = getenv("WC_DIRAC_STAGE");
-    forced = e ? atoi(e) : -1;
-  }
   if (B.uniform_bvol != 256) return 0;
+  const int forced = B.lat[0]->opt_dirac_stage;
   return forced >= 0 ? forced : (prec == P_F64 ? 1 : 0);
 }
 
@@ -461,13 +465,10 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
 }
 
 // Register caching of the block operator pays when the launch has about one work-group
-// per CU (then nothing else could hide the reload latency); WC_SAP_CACHE=0/1 forces it.
-static int sap_cache_mode(int nitems) {
-  static int forced = -2;
-  if (forced == -2) {
-    const char* e = getenv("WC_SAP_CACHE");
-    forced = e ? atoi(e) : -1;
-  }
+// per CU (then nothing else could hide the reload latency); the WC_OPT_SAP_CACHE option of
+// the batch's first context forces it on or off.
+static int sap_cache_mode(const Batch& B, int nitems) {
+  const int forced = B.lat[0]->opt_sap_cache;
   if (forced >= 0) return forced;
   return nitems <= 2 * device_cus() ? 1 : 0;
 }
@@ -499,7 +500,7 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.border = border;
   a.write_rho = wrho;
   a.write_z = wz;
-  a.cache = sap_cache_mode(it.n);
+  a.cache = sap_cache_mode(B, it.n);
   a.uniform_bvol = B.uniform_bvol;
   a.odd_rho = odd_rho;
   if (eo)
@@ -546,9 +547,49 @@ static void unpack_batch(Batch& B, int prec, const Field& f, void* const* canon,
 // ---------------------------------------------------------------------------- FGCR
 
 struct SolveSetup {
-  int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit, eo;
+  int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit, eo, stag, timing;
   double tol;
 };
+
+// Events recorded between the phases of an eagerly launched restart cycle (solver
+// parameter `timing`): the time between two marks is charged to the phase that ends at
+// the later one.
+enum Phase { PH_SAP = 0, PH_DIRAC = 1, PH_BLAS = 2 };
+struct PhaseTimer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> tag;
+  size_t n = 0;
+  double t[3] = {0.0, 0.0, 0.0};
+  PhaseTimer() = default;
+  PhaseTimer(const PhaseTimer&) = delete;
+  PhaseTimer& operator=(const PhaseTimer&) = delete;
+  ~PhaseTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  void mark(int phase, hipStream_t st) {
+    if (n == ev.size()) {
+      hipEvent_t e;
+      HIPCK(hipEventCreate(&e));
+      ev.push_back(e);
+      tag.push_back(0);
+    }
+    tag[n] = phase;
+    HIPCK(hipEventRecord(ev[n], st));
+    ++n;
+  }
+  // after the stream has reached the last mark
+  void collect() {
+    for (size_t i = 1; i < n; ++i) {
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+      t[tag[i]] += ms;
+    }
+    n = 0;
+  }
+};
+static void mark(PhaseTimer* tm, int phase, hipStream_t st) {
+  if (tm) tm->mark(phase, st);
+}
 
 static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   VecLaunch a;
@@ -563,6 +604,9 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.k = 0;
   a.maxit = s.maxit;
   a.tol = s.tol;
+  a.stag = s.stag;
+  a.hist = B.hist.as<double>();
+  a.hist_max = HIST_MAX;
   a.r = B.r.d.as<double2>();
   a.x = B.x.d.as<double2>();
   a.chi = B.d_chi.as<double2* const>();
@@ -594,6 +638,7 @@ static void prepare_solver(Batch& B, const SolveSetup& s) {
   B.sap_psi.ensure(s.sap_prec, n);
   B.sys.ensure(sizeof(SysState) * B.nsys);
   B.skip.ensure(sizeof(int) * B.nsys);
+  B.hist.ensure(sizeof(double) * HIST_MAX * B.nsys);
   // everything a captured cycle touches must exist before capture starts
   B.lats(P_F64, nullptr);
   B.lats(s.sap_prec, nullptr, s.eo != 0);
@@ -605,10 +650,11 @@ static void prepare_solver(Batch& B, const SolveSetup& s) {
 }
 
 // one restart cycle: nkv FGCR iterations; systems whose skip flag is set sit out
-static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
+static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTimer* tm = nullptr) {
   VecLaunch va = vec_launch(B, s, st);
   const int gv = persistent_grid(va.nitems, 8);
   const int* skip = B.skip.as<int>();
+  mark(tm, PH_BLAS, st);
   for (int k = 0; k < s.nkv; ++k) {
     va.k = k;
     // phi_k = |r| M_SAP(r / |r|)
@@ -620,31 +666,115 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st) {
     vs.sp = B.sap_psi.data();
     vs.sp_sc = B.sap_psi.scale();
     launch_from_sap(s.sap_prec, vs, gv, st);
+    mark(tm, PH_SAP, st);
     // chi_k = D phi_k in FP64
     run_dirac(B, P_F64, s.nr_d, B.phi[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
-    // classical Gram-Schmidt in two passes: all inner products, then the update of chi_k and r
+    mark(tm, PH_DIRAC, st);
+    // classical Gram-Schmidt: all inner products, then the update of chi_k and r; a system
+    // whose first pass cancelled takes a second pass (RED_GS2, k_gs_update2)
     launch_gs_dots(va, gv, st);
     launch_reduce(RED_GS, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
     launch_gs_update(va, gv, st);
+    launch_reduce(RED_GS2, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+    launch_gs_update2(va, gv, st);
     launch_reduce(RED_RNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+    mark(tm, PH_BLAS, st);
   }
   // x += sum alpha phi; r = b - D x in FP64
   launch_backsub(va, B.nsys, st);
   launch_x_update(va, gv, st);
+  mark(tm, PH_BLAS, st);
   run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+  mark(tm, PH_DIRAC, st);
   launch_reduce(RED_TRUE, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
+  mark(tm, PH_BLAS, st);
 }
 
 static std::string setup_key(const SolveSetup& s) {
-  char buf[160];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s,
-           s.maxit, s.eo, s.tol);
+  char buf[200];
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s,
+           s.maxit, s.eo, s.stag, s.tol);
   return buf;
+}
+
+// Key of a captured cycle: the set-up, the kernel-selecting options and the device address
+// of every buffer the cycle's launches name.  A field that another call reallocated (a
+// wider precision asked of the batch's Schwarz fields, for instance) changes the key, so
+// a graph is never replayed over memory that was freed.
+static std::string graph_key(const Batch& B, const SolveSetup& s) {
+  std::string k = setup_key(s);
+  char buf[40];
+  auto add = [&](const void* q) {
+    snprintf(buf, sizeof buf, "|%p", q);
+    k += buf;
+  };
+  add(B.x.data());
+  add(B.b.data());
+  add(B.r.data());
+  for (int i = 0; i < s.nkv; ++i) {
+    add(B.chi[i].data());
+    add(B.phi[i].data());
+  }
+  for (const Field* f : {&B.sap_rho, &B.sap_z, &B.sap_psi}) {
+    add(f->data());
+    add(f->scale());
+  }
+  for (const DevBuf* d : {&B.sys, &B.skip, &B.partials, &B.hist, &B.d_chi, &B.d_phi, &B.d_arn_v, &B.arn,
+                          &B.sys_part, &B.sys_nchunks, &B.d_lats[P_F64], &B.d_lats[s.sap_prec]})
+    add(d->p);
+  add(B.arn_vlast.data());
+  for (const auto& kv : B.dirac_items) add(kv.second.d.p);
+  for (int c = 0; c < 2; ++c)
+    for (const auto& kv : B.sap_items[c]) add(kv.second.d.p);
+  k += "|" + std::to_string(B.lat[0]->opt_sap_cache) + "," + std::to_string(B.lat[0]->opt_dirac_stage);
+  return k;
+}
+
+// what the host reads back of each system after a solve
+static void fill_stats(Batch& B, const std::vector<SysState>& hs, float ms, const double* tph,
+                       std::vector<wc_solver_stats>& stats, int* rc_out) {
+  std::vector<double> hist((size_t)HIST_MAX * B.nsys);
+  HIPCK(hipMemcpy(hist.data(), B.hist.p, sizeof(double) * hist.size(), hipMemcpyDeviceToHost));
+  int rc = WC_OK;
+  stats.resize(B.nsys);
+  for (int i = 0; i < B.nsys; ++i) {
+    wc_solver_stats& o = stats[i];
+    std::memset(&o, 0, sizeof o);
+    const SysState& S = hs[i];
+    o.iters = S.iters;
+    o.restarts = S.restarts;
+    o.breakdown = S.breakdown;
+    o.reorth = S.reorths;
+    o.stagnated = S.stagnated;
+    o.rel_true_res = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+    o.time_ms = ms;
+    o.nhist = std::min(S.restarts, HIST_MAX);
+    for (int h = 0; h < o.nhist; ++h) o.res_hist[h] = hist[(size_t)i * HIST_MAX + h];
+    o.timed = tph ? 1 : 0;
+    if (tph) {
+      o.t_setup_ms = tph[3];
+      o.t_cycles_ms = tph[4];
+      o.t_finish_ms = tph[5];
+      o.t_sap_ms = tph[PH_SAP];
+      o.t_dirac_ms = tph[PH_DIRAC];
+      o.t_blas_ms = tph[PH_BLAS];
+    }
+    if (S.breakdown)
+      o.status = WC_ERR_BREAKDOWN;
+    else if (S.bnorm2 > 0 && !(S.rnorm2 <= S.tol2))
+      o.status = WC_ERR_NOT_CONVERGED;
+    else
+      o.status = WC_OK;
+    if (rc == WC_OK && o.status != WC_OK) rc = o.status;
+  }
+  *rc_out = rc;
 }
 
 static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_graph, wc_ctx* cap_owner,
                       std::vector<wc_solver_stats>& stats, hipStream_t st) {
-  HipEvent e0, e1;
+  HipEvent e0, e1, e_setup, e_cycles;
+  std::unique_ptr<PhaseTimer> tm(s.timing ? new PhaseTimer : nullptr);
+  if (tm) use_graph = false;
   HIPCK(hipEventRecord(e0, st));
   VecLaunch va = vec_launch(B, s, st);
   const int gv = persistent_grid(va.nitems, 8);
@@ -660,10 +790,11 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
     launch_copy_f64(va, B.r.d.as<double2>(), B.b.d.as<double2>(), gv, st);
   }
   HIPCK(hipGetLastError());
+  HIPCK(hipEventRecord(e_setup, st));
 
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
-    const std::string key = setup_key(s);
+    const std::string key = graph_key(B, s);
     if (B.graph && B.graph_key == key) {
       exec = B.graph;
     } else {
@@ -683,40 +814,31 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
   for (int rs = 0; rs < max_restarts; ++rs) {
     HIPCK(hipMemcpyAsync(h_skip.data(), B.skip.p, sizeof(int) * B.nsys, hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
+    if (tm) tm->collect();
     bool all = true;
     for (int v : h_skip) all &= (v != 0);
     if (all) break;
     if (exec)
       HIPCK(hipGraphLaunch(exec, st));
     else
-      enqueue_cycle(B, s, st);
+      enqueue_cycle(B, s, st, tm.get());
     HIPCK(hipGetLastError());
   }
+  HIPCK(hipEventRecord(e_cycles, st));
   HIPCK(hipEventRecord(e1, st));
   HIPCK(hipEventSynchronize(e1));
-  float ms = 0.f;
+  float ms = 0.f, ms_setup = 0.f, ms_cycles = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  HIPCK(hipEventElapsedTime(&ms_setup, e0, e_setup));
+  HIPCK(hipEventElapsedTime(&ms_cycles, e_setup, e_cycles));
+  double tph[6] = {0, 0, 0, ms_setup, ms_cycles, 0};
+  if (tm)
+    for (int q = 0; q < 3; ++q) tph[q] = tm->t[q];
 
   std::vector<SysState> hs(B.nsys);
   HIPCK(hipMemcpy(hs.data(), B.sys.p, sizeof(SysState) * B.nsys, hipMemcpyDeviceToHost));
   int rc = WC_OK;
-  stats.resize(B.nsys);
-  for (int i = 0; i < B.nsys; ++i) {
-    wc_solver_stats& o = stats[i];
-    const SysState& S = hs[i];
-    o.iters = S.iters;
-    o.restarts = S.restarts;
-    o.breakdown = S.breakdown;
-    o.rel_true_res = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
-    o.time_ms = ms;
-    if (S.breakdown)
-      o.status = WC_ERR_BREAKDOWN;
-    else if (S.bnorm2 > 0 && !(S.rnorm2 <= S.tol2))
-      o.status = WC_ERR_NOT_CONVERGED;
-    else
-      o.status = WC_OK;
-    if (rc == WC_OK && o.status != WC_OK) rc = o.status;
-  }
+  fill_stats(B, hs, ms, tm ? tph : nullptr, stats, &rc);
   return rc;
 }
 
@@ -727,6 +849,8 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   require(p.tol > 0 && p.maxit >= 1, WC_ERR_ARG, "tol must be > 0 and maxit >= 1");
   require(p.eo == 0 || p.eo == 1, WC_ERR_ARG, "eo must be 0 or 1");
   require(p.dagger == 0 || p.dagger == 1, WC_ERR_ARG, "dagger must be 0 or 1");
+  require(p.stag >= 0, WC_ERR_ARG, "stag must be >= 0");
+  require(p.timing == 0 || p.timing == 1, WC_ERR_ARG, "timing must be 0 or 1");
   SolveSetup s;
   s.nkv = p.nkv;
   s.ncy = p.ncy;
@@ -735,6 +859,8 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   s.tol = p.tol;
   s.maxit = p.maxit;
   s.eo = p.eo ? 1 : 0;
+  s.stag = p.stag;
+  s.timing = p.timing;
   s.nr_d = pick_nr(c, max_nrhs, P_F64, false, p.nr_dirac);
   s.nr_s = pick_nr(c, max_nrhs, p.sap_prec, true, p.nr_sap, s.eo);
   return s;
@@ -898,8 +1024,14 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
       launch_arn_init(va, gv, st);
     }
     if (use_graph) {
-      char key[200];
-      snprintf(key, sizeof key, "%s|%d", setup_key(s).c_str(), j0);
+      const std::string base = graph_key(B, s);
+      if (base != B.arn_key) {
+        // a buffer of the captured cycles moved: none of them may run again
+        for (auto& kv : B.arn_graphs) HIPCK(hipGraphExecDestroy(kv.second));
+        B.arn_graphs.clear();
+        B.arn_key = base;
+      }
+      const std::string key = std::to_string(j0);
       auto it = B.arn_graphs.find(key);
       if (it == B.arn_graphs.end()) {
         if (!cap_owner->cap) HIPCK(hipStreamCreateWithFlags(&cap_owner->cap, hipStreamNonBlocking));
@@ -978,23 +1110,7 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
   get_sys();
   int rc = WC_OK;
-  stats.resize(n);
-  for (int i = 0; i < n; ++i) {
-    wc_solver_stats& o = stats[i];
-    const SysState& S = hs[i];
-    o.iters = S.iters;
-    o.restarts = S.restarts;
-    o.breakdown = S.breakdown;
-    o.rel_true_res = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
-    o.time_ms = ms;
-    if (S.breakdown)
-      o.status = WC_ERR_BREAKDOWN;
-    else if (S.bnorm2 > 0 && !(S.rnorm2 <= S.tol2))
-      o.status = WC_ERR_NOT_CONVERGED;
-    else
-      o.status = WC_OK;
-    if (rc == WC_OK && o.status != WC_OK) rc = o.status;
-  }
+  fill_stats(B, hs, ms, nullptr, stats, &rc);
   return rc;
 }
 
@@ -1093,6 +1209,35 @@ void wc_default_params(wc_solver_params* p) {
   p->nr_sap = 0;
   p->eo = 0;
   p->dagger = 0;
+  p->stag = 3;
+  p->timing = 0;
+}
+
+int wc_set_option(wc_ctx* c, int option, int value) {
+  return guarded([&] {
+    require(c, WC_ERR_ARG, "null context");
+    require(value >= -1 && value <= 1, WC_ERR_ARG, "option value must be -1, 0 or 1");
+    if (option == WC_OPT_SAP_CACHE)
+      c->opt_sap_cache = value;
+    else if (option == WC_OPT_DIRAC_STAGE)
+      c->opt_dirac_stage = value;
+    else
+      require(false, WC_ERR_ARG, "unknown option");
+  });
+}
+
+int wc_set_tiles(wc_ctx* c, int prec, int nr_dirac, int nr_sap, int nr_sap_eo) {
+  return guarded([&] {
+    require(c, WC_ERR_ARG, "null context");
+    check_prec(prec);
+    const int smax = prec == P_F64 ? 1 : 2;
+    require(nr_dirac >= 0 && nr_dirac <= 4, WC_ERR_ARG, "nr_dirac must be in 0..4");
+    require(nr_sap >= 0 && nr_sap <= smax && nr_sap_eo >= 0 && nr_sap_eo <= smax, WC_ERR_ARG,
+            "block-solver tiles must be in 0..2 (0..1 for FP64)");
+    c->nr_dirac[prec] = nr_dirac;
+    c->nr_sap[prec] = nr_sap;
+    c->nr_sap_eo[prec] = nr_sap_eo;
+  });
 }
 
 int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const void* U, int bc_t, void* stream) {
@@ -1276,7 +1421,12 @@ static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<
       for (size_t i = 0; i < stats.size(); ++i) st_out[i] = stats[i];
     if (rc != WC_OK) {
       const char* what = kdefl >= 0 ? "FGMRES-DR" : "FGCR";
-      g_last_error = std::string(what) + (rc == WC_ERR_BREAKDOWN ? " breakdown" : " did not converge within maxit");
+      bool stagnated = false;
+      for (const wc_solver_stats& o : stats) stagnated |= o.stagnated != 0;
+      g_last_error = std::string(what) + (rc == WC_ERR_BREAKDOWN ? " breakdown"
+                                          : stagnated ? " stagnated: the true residual did not drop over "
+                                                            + std::to_string(p->stag) + " restarts"
+                                                      : " did not converge within maxit");
     }
   });
   return grc != WC_OK ? grc : rc;
@@ -1344,6 +1494,23 @@ int wc_link_grad(wc_ctx* c, void* G, const void* Y, const void* X, int nrhs, dou
   });
 }
 
+// Y = D^-dag phi = g5 D^-1 g5 phi (gamma5-hermiticity), then X = D^-1 Y, into the
+// caller's or the library's buffers; returns the first solve status that is not WC_OK.
+static int action_solves(wc_ctx* c, const void* phi, const wc_solver_params* p, void* y, void* x, void* tmp,
+                         wc_solver_stats* s2, void* stream) {
+  hipStream_t st_ = S(stream);
+  wc_solver_params q = *p;
+  q.x0_given = 0;
+  q.dagger = 0;
+  launch_gamma5_canon(c->g.V, phi, tmp, st_);
+  const int r1 = wc_fgcr_solve(c, y, tmp, 1, &q, &s2[0], stream);
+  require(r1 == WC_OK || r1 == WC_ERR_NOT_CONVERGED || r1 == WC_ERR_BREAKDOWN, r1, g_last_error);
+  launch_gamma5_canon(c->g.V, y, y, st_);
+  const int r2 = wc_fgcr_solve(c, x, y, 1, &q, &s2[1], stream);
+  require(r2 == WC_OK || r2 == WC_ERR_NOT_CONVERGED || r2 == WC_ERR_BREAKDOWN, r2, g_last_error);
+  return r1 != WC_OK ? r1 : r2;
+}
+
 int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_solver_stats* st, void* Yout,
              void* Xout, void* stream) {
   int rc_solve = WC_OK;
@@ -1356,18 +1523,8 @@ int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_
     y.ensure(bytes);
     x.ensure(bytes);
     tmp.ensure(bytes);
-    // Y = D^-dag phi = g5 D^-1 g5 phi (gamma5-hermiticity), then X = D^-1 Y
-    wc_solver_params q = *p;
-    q.x0_given = 0;
-    q.dagger = 0;
     wc_solver_stats s2[2];
-    launch_gamma5_canon(c->g.V, phi, tmp.p, st_);
-    int r1 = wc_fgcr_solve(c, y.p, tmp.p, 1, &q, &s2[0], stream);
-    require(r1 == WC_OK || r1 == WC_ERR_NOT_CONVERGED || r1 == WC_ERR_BREAKDOWN, r1, g_last_error);
-    launch_gamma5_canon(c->g.V, y.p, y.p, st_);
-    int r2 = wc_fgcr_solve(c, x.p, y.p, 1, &q, &s2[1], stream);
-    require(r2 == WC_OK || r2 == WC_ERR_NOT_CONVERGED || r2 == WC_ERR_BREAKDOWN, r2, g_last_error);
-    rc_solve = r1 != WC_OK ? r1 : r2;
+    rc_solve = action_solves(c, phi, p, y.p, x.p, tmp.p, s2, stream);
     DevBuf xi;
     if (c->csw != 0.0) xi.ensure(sizeof(double2) * 54 * (size_t)c->g.V);
     launch_force(c->dims, c->bc_t, c->Ucanon.p, y.p, x.p, 1, c->csw, 1.0, 1, xi.p, F, st_);
@@ -1381,6 +1538,38 @@ int wc_force(wc_ctx* c, void* F, const void* phi, const wc_solver_params* p, wc_
     }
   });
   return rc != WC_OK ? rc : rc_solve;
+}
+
+int wc_pseudofermion_action(wc_ctx* c, const void* phi, const wc_solver_params* p, double* Sout, void* Y, void* X,
+                            wc_solver_stats* st, void* stream) {
+  int rc_solve = WC_OK;
+  int rc = guarded([&] {
+    require(c && phi && p && Sout && Y && X, WC_ERR_ARG, "bad argument");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    hipStream_t st_ = S(stream);
+    DevBuf tmp, work;
+    tmp.ensure((size_t)c->g.V * 192);
+    work.ensure(sizeof(double) * 1025);
+    wc_solver_stats s2[2];
+    rc_solve = action_solves(c, phi, p, Y, X, tmp.p, s2, stream);
+    launch_norm2_canon((long long)c->g.V * 12, Y, work.as<double>(), st_);
+    HIPCK(hipGetLastError());
+    HIPCK(hipMemcpyAsync(Sout, work.p, sizeof(double), hipMemcpyDeviceToHost, st_));
+    HIPCK(hipStreamSynchronize(st_));
+    if (st) {
+      st[0] = s2[0];
+      st[1] = s2[1];
+    }
+  });
+  return rc != WC_OK ? rc : rc_solve;
+}
+
+int wc_spinor_scale(wc_ctx* c, void* out, const void* in, int nrhs, double coef, void* stream) {
+  return guarded([&] {
+    require(c && out && in && nrhs >= 1, WC_ERR_ARG, "bad argument");
+    launch_scale_canon((long long)c->g.V * 12 * nrhs, coef, in, out, S(stream));
+    HIPCK(hipGetLastError());
+  });
 }
 
 // Mean time per launch of f: `iters` launches captured into one hipGraph (so host-side
@@ -1457,36 +1646,58 @@ int wc_bench_sap(wc_ctx* c, int prec, int nrhs, int nmr, int eo, int iters, doub
   });
 }
 
-int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[2], void* stream) {
+int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[4], void* stream) {
   return guarded([&] {
     require(c && nrhs >= 1, WC_ERR_ARG, "bad argument");
     check_prec(prec);
     const int cands[3] = {1, 2, 4};
-    double best_d = 1e30, best_s = 1e30, best_e = 1e30;
-    int nd = 1, ns = 1, ne = 1;
+    // D tiles: in prec and, for the outer solver, in FP64
+    std::vector<int> dps = {prec};
+    if (prec != P_F64) dps.push_back(P_F64);
+    for (int dp : dps) {
+      double best = 1e30;
+      int nd = 1;
+      for (int nr : cands) {
+        if (nr > nrhs) continue;
+        c->nr_dirac[dp] = nr;
+        double t = 0;
+        const int rc = wc_bench_dirac(c, dp, nrhs, WC_FULL, 20, &t, stream);
+        require(rc == WC_OK, rc, g_last_error);
+        if (t < best) {
+          best = t;
+          nd = nr;
+        }
+      }
+      c->nr_dirac[dp] = nd;
+    }
+    // block-solver tiles of both block solvers in prec
+    double best_s = 1e30, best_e = 1e30;
+    int ns = 1, ne = 1;
     for (int nr : cands) {
-      if (nr > nrhs) continue;
-      c->nr_dirac[prec] = nr;
+      if (nr > nrhs || nr > (prec == P_F64 ? 1 : 2)) continue;
       double t = 0;
-      int rc = wc_bench_dirac(c, prec, nrhs, WC_FULL, 20, &t, stream);
-      require(rc == WC_OK, rc, g_last_error);
-      if (t < best_d) { best_d = t; nd = nr; }
-      if (nr > (prec == P_F64 ? 1 : 2)) continue;
       c->nr_sap[prec] = nr;
-      rc = wc_bench_sap(c, prec, nrhs, 4, 0, 10, &t, stream);
+      int rc = wc_bench_sap(c, prec, nrhs, 4, 0, 10, &t, stream);
       require(rc == WC_OK, rc, g_last_error);
-      if (t < best_s) { best_s = t; ns = nr; }
+      if (t < best_s) {
+        best_s = t;
+        ns = nr;
+      }
       c->nr_sap_eo[prec] = nr;
       rc = wc_bench_sap(c, prec, nrhs, 4, 1, 10, &t, stream);
       require(rc == WC_OK, rc, g_last_error);
-      if (t < best_e) { best_e = t; ne = nr; }
+      if (t < best_e) {
+        best_e = t;
+        ne = nr;
+      }
     }
-    c->nr_dirac[prec] = nd;
     c->nr_sap[prec] = ns;
     c->nr_sap_eo[prec] = ne;
     if (nr_out) {
-      nr_out[0] = nd;
-      nr_out[1] = ns;
+      nr_out[0] = c->nr_dirac[prec];
+      nr_out[1] = c->nr_dirac[P_F64];
+      nr_out[2] = ns;
+      nr_out[3] = ne;
     }
   });
 }
@@ -1545,7 +1756,7 @@ int wc_autotune_block(wc_ctx* c, const wc_solver_params* p, int block_out[4], vo
 
 const char* wc_last_error(void) { return g_last_error.c_str(); }
 
-int wc_version(void) { return 100; }
+int wc_version(void) { return 200; }
 
 void wc_destroy(wc_ctx* c) { delete c; }
 

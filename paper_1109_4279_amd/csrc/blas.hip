@@ -51,9 +51,12 @@ __global__ __launch_bounds__(WG) void k_from_sap(VecLaunch a) {
 
 // One pass over chi_k, r and chi_0..chi_{k-1}: partial sums of
 //   a_l = <chi_l, chi_k>, e_l = <chi_l, r> (l < k), |chi_k|^2 and <chi_k, r>.
-// With them the reduction gets the classical Gram-Schmidt coefficients a_lk, the norm
-// b_k of chi_k - sum a_lk chi_l (|chi_k|^2 - sum |a_lk|^2, the chi_l being orthonormal)
-// and c_k = <chi_k - sum a_lk chi_l, r> / b_k without a second pass.
+// With them the reduction gets the classical Gram-Schmidt coefficients a_lk, the squared
+// norm |chi_k|^2 - sum |a_lk|^2 of chi_k - sum a_lk chi_l (the chi_l being orthonormal)
+// and c_k = <chi_k - sum a_lk chi_l, r> / b_k without another pass over the vectors.  The
+// subtraction is exact enough only while it keeps a fair share of |chi_k|^2; below half of
+// it (the criterion of Daniel, Gragg, Kaufman and Stewart, Math. Comp. 30 (1976) 772) the
+// reduction asks for a second classical pass instead (k_gs_update, RED_GS2, k_gs_update2).
 // Partial layout per chunk: [2k a][2k e][|chi_k|^2][2 <chi_k, r>].
 __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (4 * NKV_MAX + 4)];
@@ -114,9 +117,13 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   }
 }
 
-// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2
+// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2.
+// A system flagged by the reduction for a second pass (S.reorth) instead stores
+// chi_k' = chi_k - sum_l a_lk chi_l and the partial sums of the second pass,
+//   a2_l = <chi_l, chi_k'> (l < k), |chi_k'|^2 and <chi_k', r>,
+// as [2k a2][|chi_k'|^2][2 <chi_k', r>]; r is left for k_gs_update2.
 __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
-  __shared__ double lds[(WG / 64)];
+  __shared__ double lds[(WG / 64) * (2 * NKV_MAX + 4)];
   const int k = a.k;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
@@ -126,6 +133,95 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
     for (int l = 0; l < k; ++l) {
       const double2 al = S.a[l * NKV_MAX + k];
       const cplx<double> m = {-al.x, -al.y};
+      Spinor<double> cl = ld64_nt(a.chi[l], v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cmac(ck.c[i][c], m, cl.c[i][c]);
+    }
+    if (S.reorth) {
+      const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+      constexpr int LD = 2 * NKV_MAX + 4;
+      if (v.valid)
+        st64(a.chi[k], v, ck);
+      else
+        zero(ck);
+      Spinor<double> r = ld64(a.r, v);
+      if (!v.valid) zero(r);
+      auto put = [&](int j, double x) {
+        x = wave_sum(x);
+        if (lane == 0) lds[wid * LD + j] = x;
+      };
+      for (int l = 0; l < k; ++l) {
+        const Spinor<double> cl = ld64_nt(a.chi[l], v);
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cplx<double> x = cl.c[i][c];
+            re += x.re * ck.c[i][c].re + x.im * ck.c[i][c].im;
+            im += x.re * ck.c[i][c].im - x.im * ck.c[i][c].re;
+          }
+        put(2 * l, re);
+        put(2 * l + 1, im);
+      }
+      double n2 = 0.0, cre = 0.0, cim = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const cplx<double> x = ck.c[i][c];
+          n2 += x.re * x.re + x.im * x.im;
+          cre += x.re * r.c[i][c].re + x.im * r.c[i][c].im;
+          cim += x.re * r.c[i][c].im - x.im * r.c[i][c].re;
+        }
+      put(2 * k, n2);
+      put(2 * k + 1, cre);
+      put(2 * k + 2, cim);
+      __syncthreads();
+      for (int j = threadIdx.x; j < 2 * k + 3; j += WG) {
+        double t = 0.0;
+        for (int w = 0; w < WG / 64; ++w) t += lds[w * LD + j];
+        a.partials[(size_t)v.part * a.pw + j] = t;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double ib = 1.0 / S.bk[k];
+    const cplx<double> mc = {-S.ck[k].x, -S.ck[k].y};
+    double vals[1] = {0.0};
+    if (v.valid) {
+      Spinor<double> r = ld64(a.r, v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ck.c[i][c] = ib * ck.c[i][c];
+          cmac(r.c[i][c], mc, ck.c[i][c]);
+          vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
+        }
+      st64(a.chi[k], v, ck);
+      st64(a.r, v, r);
+    }
+    put_partial<1>(a, v, vals, lds);
+    __syncthreads();
+  }
+}
+
+// Second Gram-Schmidt pass of the flagged systems: chi_k <- (chi_k' - sum_l a2_l chi_l) / b_k;
+// r <- r - c_k chi_k; partial |r|^2.  Other systems were finished by k_gs_update.
+__global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
+  __shared__ double lds[(WG / 64)];
+  const int k = a.k;
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    if (a.skip[v.sys]) continue;
+    const SysState& S = a.sys[v.sys];
+    if (!S.reorth) continue;
+    Spinor<double> ck = ld64(a.chi[k], v);
+    for (int l = 0; l < k; ++l) {
+      const cplx<double> m = {-S.a2[l].x, -S.a2[l].y};
       Spinor<double> cl = ld64_nt(a.chi[l], v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -214,13 +310,24 @@ __global__ __launch_bounds__(WG) void k_zero_if_b0(VecLaunch a, double2* x) {
 
 // ------------------------------------------------------------------ per-system reductions
 
+// a vanishing or non-finite direction ends the system's solve with a breakdown
+WC_D void gs_breakdown(SysState& S, int* skip, int sys, int k) {
+  S.breakdown = 1;
+  S.cycle_done = 1;
+  S.reorth = 0;
+  S.bk[k] = 1.0;
+  S.ck[k] = make_double2(0.0, 0.0);
+  skip[sys] = 1;
+}
+
 __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
   __shared__ double lds[RWG];
   const int sys = blockIdx.x;
   SysState& S = a.sys[sys];
-  const int nv = op == RED_GS ? 4 * a.k + 3 : 1;
+  const int nv = op == RED_GS ? 4 * a.k + 3 : (op == RED_GS2 ? 2 * a.k + 3 : 1);
   const bool global_op = (op == RED_TRUE || op == RED_BNORM || op == RED_INITR);
   if (!global_op && (a.skip[sys] != 0)) return;
+  if (op == RED_GS2 && !S.reorth) return;
   if ((op == RED_TRUE || op == RED_INITR) && S.converged) return;
   if (nv == 0) return;
   sum_partials(a.partials, a.pw, sys_part[sys], sys_nchunks[sys], nv, lds);
@@ -229,23 +336,54 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
   const int k = a.k;
   switch (op) {
     case RED_GS: {
-      // a_lk, b_k^2 = |chi_k|^2 - sum |a_lk|^2, c_k = (<chi_k, r> - sum conj(a_lk) <chi_l, r>) / b_k
-      double b2 = sum[4 * k], cre = sum[4 * k + 1], cim = sum[4 * k + 2];
+      // a_lk, s = |chi_k|^2 - sum |a_lk|^2, c_k = (<chi_k, r> - sum conj(a_lk) <chi_l, r>) / b_k
+      const double n2 = sum[4 * k];
+      double b2 = n2, cre = sum[4 * k + 1], cim = sum[4 * k + 2];
       for (int l = 0; l < k; ++l) {
         const double are = sum[2 * l], aim = sum[2 * l + 1];
         const double ere = sum[2 * k + 2 * l], eim = sum[2 * k + 2 * l + 1];
         S.a[l * NKV_MAX + k] = make_double2(are, aim);
+        S.e[l] = make_double2(ere, eim);
+        b2 -= are * are + aim * aim;
+        cre -= are * ere + aim * eim;
+        cim -= are * eim - aim * ere;
+      }
+      S.n2_first = n2;
+      S.a[k * NKV_MAX + k] = make_double2(0.0, 0.0);
+      if (!(n2 > 0.0) || !isfinite(n2) || !isfinite(b2)) {
+        gs_breakdown(S, a.skip, sys, k);
+        break;
+      }
+      // one pass kept more than half of |chi_k|^2: b_k from the subtraction
+      S.reorth = !(b2 > 0.5 * n2);
+      if (S.reorth) {
+        S.reorths += 1;
+        break;
+      }
+      const double b = sqrt(b2);
+      S.bk[k] = b;
+      S.ck[k] = make_double2(cre / b, cim / b);
+      break;
+    }
+    case RED_GS2: {
+      // second pass: a_lk += a2_l, b_k^2 = |chi_k'|^2 - sum |a2_l|^2,
+      // c_k = (<chi_k', r> - sum conj(a2_l) <chi_l, r>) / b_k
+      if (!S.reorth) break;
+      double b2 = sum[2 * k], cre = sum[2 * k + 1], cim = sum[2 * k + 2];
+      for (int l = 0; l < k; ++l) {
+        const double are = sum[2 * l], aim = sum[2 * l + 1];
+        const double ere = S.e[l].x, eim = S.e[l].y;
+        S.a2[l] = make_double2(are, aim);
+        const double2 a1 = S.a[l * NKV_MAX + k];
+        S.a[l * NKV_MAX + k] = make_double2(a1.x + are, a1.y + aim);
         b2 -= are * are + aim * aim;
         cre -= are * ere + aim * eim;
         cim -= are * eim - aim * ere;
       }
       const double b = sqrt(b2);
-      if (!(b2 > 1e-24 * sum[4 * k]) || !isfinite(b)) {
-        S.breakdown = 1;
-        S.cycle_done = 1;
-        S.bk[k] = 1.0;
-        S.ck[k] = make_double2(0.0, 0.0);
-        a.skip[sys] = 1;
+      // a direction that keeps less than 1e-14 of |chi_k| after two passes is rounding noise
+      if (!(b2 > 1e-28 * S.n2_first) || !isfinite(b)) {
+        gs_breakdown(S, a.skip, sys, k);
         break;
       }
       S.bk[k] = b;
@@ -271,26 +409,40 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       S.k_done = 0;
       S.iters = 0;
       S.restarts = 0;
+      S.reorth = 0;
+      S.reorths = 0;
+      S.stall = 0;
+      S.stagnated = 0;
+      S.prev_true2 = sum[0];
       S.breakdown = !isfinite(sum[0]);
       if (S.breakdown) S.converged = 1;
       a.skip[sys] = S.converged;
       break;
     case RED_INITR:  // residual of a given initial guess
       S.rnorm2 = sum[0];
+      S.prev_true2 = sum[0];
       if (!isfinite(sum[0])) S.breakdown = 1;
       S.converged = (sum[0] <= S.tol2) || S.breakdown;
       S.cycle_done = S.converged;
       a.skip[sys] = S.converged;
       break;
-    case RED_TRUE:
+    case RED_TRUE: {
       S.rnorm2 = sum[0];
       S.restarts += 1;
       if (!isfinite(sum[0])) S.breakdown = 1;
-      S.converged = (sum[0] <= S.tol2) || S.breakdown || S.iters >= a.maxit;
+      if (a.hist && S.restarts <= a.hist_max)
+        a.hist[(size_t)sys * a.hist_max + S.restarts - 1] = S.bnorm2 > 0.0 ? sqrt(sum[0] / S.bnorm2) : 0.0;
+      // stagnation: the true residual of a restart is no smaller than the previous one
+      const bool done = (sum[0] <= S.tol2) || S.breakdown || S.iters >= a.maxit;
+      S.stall = (S.restarts > 1 && !(sum[0] < S.prev_true2)) ? S.stall + 1 : 0;
+      S.prev_true2 = sum[0];
+      if (!done && a.stag > 0 && S.stall >= a.stag) S.stagnated = 1;
+      S.converged = done || S.stagnated;
       S.cycle_done = S.converged;
       S.k_done = 0;
       a.skip[sys] = S.converged;
       break;
+    }
   }
 }
 
@@ -336,6 +488,7 @@ void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
 }
 void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_dots, a, grid, st); }
 void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update, a, grid, st); }
+void launch_gs_update2(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update2, a, grid, st); }
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_x_update, a, grid, st); }
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(grid), dim3(WG), 0, st, a, v);

@@ -453,6 +453,48 @@ void launch_gamma5_f64(void* f, long long V, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_gamma5_f64, grid, dim3(WG), 0, st, (double2*)f, V, nrhs);
 }
 
+// out = coef * in on n canonical complex128 values
+__global__ __launch_bounds__(WG) void k_scale_canon(long long n, double coef, const double2* in, double2* out) {
+  const long long i = (long long)blockIdx.x * WG + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = in[i];
+  out[i] = make_double2(coef * v.x, coef * v.y);
+}
+
+void launch_scale_canon(long long n, double coef, const void* in, void* out, hipStream_t st) {
+  dim3 grid((unsigned)((n + WG - 1) / WG));
+  hipLaunchKernelGGL(k_scale_canon, grid, dim3(WG), 0, st, n, coef, (const double2*)in, (double2*)out);
+}
+
+// |v|^2 of n canonical complex128 values, deterministically: each of `nblk` work-groups
+// sums a strided share into partial[blk]; then one work-group adds the partials in order.
+constexpr int NORM_BLOCKS = 1024;
+__global__ __launch_bounds__(WG) void k_norm2_canon(long long n, const double2* v, double* partial) {
+  __shared__ double lds[WG / 64];
+  double t = 0.0;
+  for (long long i = (long long)blockIdx.x * WG + threadIdx.x; i < n; i += (long long)gridDim.x * WG) {
+    const double2 x = v[i];
+    t += x.x * x.x + x.y * x.y;
+  }
+  double vals[1] = {t};
+  block_sum<1>(vals, lds);
+  if (threadIdx.x == 0) partial[blockIdx.x] = vals[0];
+}
+__global__ __launch_bounds__(WG) void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double lds[WG / 64];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < n; i += WG) t += partial[i];
+  double vals[1] = {t};
+  block_sum<1>(vals, lds);
+  if (threadIdx.x == 0) out[0] = vals[0];
+}
+
+// out[0] = |v|^2; `work` holds NORM_BLOCKS + 1 doubles
+void launch_norm2_canon(long long n, const void* v, double* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2_canon, dim3(NORM_BLOCKS), dim3(WG), 0, st, n, (const double2*)v, work + 1);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(WG), 0, st, (const double*)(work + 1), NORM_BLOCKS, work);
+}
+
 void launch_gamma5_canon(long long nsite, const void* src, void* dst, hipStream_t st) {
   dim3 grid((unsigned)((nsite + WG - 1) / WG));
   hipLaunchKernelGGL(k_gamma5_canon, grid, dim3(WG), 0, st, nsite, (const double2*)src, (double2*)dst);

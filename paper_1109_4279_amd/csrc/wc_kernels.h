@@ -5,7 +5,8 @@
 
 namespace wc {
 
-constexpr int NKV_MAX = 32;  // largest FGCR restart length
+constexpr int NKV_MAX = 32;   // largest FGCR restart length
+constexpr int HIST_MAX = 64;  // restarts whose true residual a solve reports
 
 // ----------------------------------------------------------------- D_w
 struct DiracLaunch {
@@ -87,7 +88,15 @@ struct SysState {
   int restarts;
   int breakdown;
   double sap_scale;    // |r| at the current SAP input
-  double2 a[NKV_MAX * NKV_MAX];  // a[l * NKV_MAX + k] = <chi_l, chi_k>
+  int reorth;          // the current direction takes a second Gram-Schmidt pass
+  int reorths;         // second passes taken in this solve
+  double n2_first;     // |chi_k|^2 before the first pass
+  double prev_true2;   // true |r|^2 of the previous restart (stagnation test)
+  int stall;           // consecutive restarts whose true residual did not drop
+  int stagnated;       // the solve stopped because the true residual stagnated
+  double2 a[NKV_MAX * NKV_MAX];  // a[l * NKV_MAX + k] = <chi_l, chi_k> (both passes)
+  double2 e[NKV_MAX];            // <chi_l, r> at the current iteration
+  double2 a2[NKV_MAX];           // second-pass coefficients of the current iteration
   double bk[NKV_MAX];
   double2 ck[NKV_MAX];
   double2 alpha[NKV_MAX];
@@ -123,6 +132,10 @@ struct VecLaunch {
   int k;                   // iteration index inside the cycle
   int maxit;               // cap on FGCR iterations per system
   double tol;              // relative residual target
+  int stag;                // restarts in a row without a drop of the true residual that stop
+                           // a system (0: never)
+  double* hist;            // [nsys][hist_max] relative true residual after each restart (or null)
+  int hist_max;
   // F64 batched fields
   double2* r;
   double2* x;
@@ -136,14 +149,18 @@ struct VecLaunch {
 void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
 void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
 void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, <chi_l, r>, |chi_k|^2, <chi_k, r>
-void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);   // chi_k = (chi_k - sum a_lk chi_l)/b_k; r -= c_k chi_k; |r|^2
+// chi_k = (chi_k - sum a_lk chi_l)/b_k; r -= c_k chi_k; |r|^2.  A system whose first pass
+// cancelled (reorth) instead keeps chi_k - sum a_lk chi_l and its second-pass dots, and
+// launch_gs_update2 finishes it after the RED_GS2 reduction.
+void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);
+void launch_gs_update2(const VecLaunch& a, int grid, hipStream_t st);
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials
 void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st);
 void launch_zero_if_b0(const VecLaunch& a, double2* x, int grid, hipStream_t st);  // x = 0 where |b| = 0
 
 // per-system reductions and scalar steps (one work-group per system)
-enum ReduceOp { RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5 };
+enum ReduceOp { RED_GS = 1, RED_RNORM = 2, RED_TRUE = 3, RED_BNORM = 4, RED_INITR = 5, RED_GS2 = 6 };
 void launch_reduce(int op, const VecLaunch& a, int nsys, const int* sys_part, const int* sys_nchunks,
                    hipStream_t st);
 void launch_backsub(const VecLaunch& a, int nsys, hipStream_t st);

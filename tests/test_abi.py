@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     # the Python binding declares exactly the header's entry points
     assert sorted(_lib.exported_symbols()) == _declared()
     lib2 = _lib.load()
-    assert lib2.wc_version() == 100
+    assert lib2.wc_version() == 200
 
 
 def _param_counts():
@@ -58,13 +58,46 @@ def _struct_fields(name):
     end = re.search(r"\}\s*" + name + ";", src).start()
     body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    return [re.findall(r"(\w+)\s*$", d.strip())[0] for d in body.split(";") if d.strip()]
+    decls = [re.sub(r"\[[^\]]*\]\s*$", "", d.strip()) for d in body.split(";") if d.strip()]
+    return [re.findall(r"(\w+)\s*$", d)[0] for d in decls]
 
 
 def test_binding_structs_match_header():
     from paper_1109_4279_amd import _lib
     assert [f for f, _ in _lib.SolverParams._fields_] == _struct_fields("wc_solver_params")
     assert [f for f, _ in _lib.SolverStats._fields_] == _struct_fields("wc_solver_stats")
+    src = open(HEADER).read()
+    assert int(re.search(r"#define WC_HIST_MAX (\d+)", src).group(1)) == _lib.HIST_MAX
+    for name, value in _lib.OPTIONS.items():
+        assert re.search(r"WC_OPT_%s = %d\b" % (name.upper(), value), src), name
+
+
+def test_struct_sizes_match_a_c_compiler(tmp_path):
+    """sizeof and field offsets of the two parameter structs as gcc lays them out equal the
+    ctypes layout the binding uses."""
+    import shutil
+    import subprocess
+    from paper_1109_4279_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = []
+    for cname, py in (("wc_solver_params", _lib.SolverParams), ("wc_solver_stats", _lib.SolverStats)):
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"wc.h\"\nint main(void) {\n"
+                   + "\n".join(lines) + "\n  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    cc = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                        capture_output=True, text=True, timeout=120)
+    assert cc.returncode == 0, cc.stderr
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               timeout=60).stdout.splitlines())
+    for cname, py in (("wc_solver_params", _lib.SolverParams), ("wc_solver_stats", _lib.SolverStats)):
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
 
 
 def test_default_params_and_error_text():
@@ -72,7 +105,8 @@ def test_default_params_and_error_text():
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("libwc.so not built")
     p = default_params()
-    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo, p.dagger) == (16, 5, 4, 1, 10000, 0, 0)
+    assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo, p.dagger, p.stag, p.timing) == \
+        (16, 5, 4, 1, 10000, 0, 0, 3, 0)
     assert abs(p.tol - 1e-10) < 1e-25
     lib = _lib.load()
     # argument errors are reported without touching a device
@@ -156,4 +190,4 @@ int main(void) {{
     assert cc.returncode == 0, cc.stderr
     run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert run.returncode == 0, (run.returncode, run.stderr)
-    assert run.stdout.strip() == "100"
+    assert run.stdout.strip() == "200"

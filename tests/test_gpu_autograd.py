@@ -77,3 +77,28 @@ def test_action_gradient_matches_oracle_force():
     F = -0.5 * force.traceless_antihermitian(np.einsum("...ab,...cb->...ac", Un, np.conj(G)))
     Fo = force.lie_force(Un, K)
     assert rel(F, Fo) < 1e-9
+
+
+@pytest.mark.timeout(300)
+def test_action_gradient_16c32_matches_the_force():
+    """16^3 x 32 (the force workload): the autograd gradient of the pseudofermion action,
+    projected on the Lie algebra, equals the library's force, and the action the library
+    returns is |Y|^2 of the Y it returns."""
+    import torch
+
+    import paper_1109_4279_amd as wc
+    from paper_1109_4279_amd.autograd import pseudofermion_action
+    dims, block, m0, csw = (32, 16, 16, 16), (4, 4, 4, 4), -0.1, 1.0
+    Un = gauge(dims)
+    phi = synth.gaussian_spinor(dims, seed=synth.FORCE_PHI_SEED)
+    kw = dict(tol=1e-12, sap_prec="f64", eo=1)
+    U = to_dev(Un).requires_grad_(True)
+    S = pseudofermion_action(U, to_dev(phi), block=block, m0=m0, csw=csw, **kw)
+    (G,) = torch.autograd.grad(S, U)
+    lat = wc.Lattice(to_dev(Un), block=block, m0=m0, csw=csw)
+    F, Y, X, st = lat.force(to_dev(phi), **kw)
+    assert all(s["status"] == 0 for s in st)
+    Y = to_np(Y)
+    assert S.item() == pytest.approx(np.vdot(Y, Y).real, rel=1e-12)
+    Fg = -0.5 * force.traceless_antihermitian(np.einsum("...ab,...cb->...ac", Un, np.conj(to_np(G))))
+    assert rel(Fg, to_np(F)) < 1e-9

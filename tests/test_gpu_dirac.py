@@ -192,3 +192,18 @@ def test_binding_checks_tensor_arguments():
     out = lat.new_spinor(2)
     assert lat.apply_D(x, out=out) is out
     assert np.array_equal(to_np(out), to_np(lat.apply_D(x)))
+
+
+def test_clover_constant_flux_closed_form():
+    """The library's clover blocks on a constant abelian flux equal the closed form
+    (4 + m0) - (c_sw / 2) sin(phi) sigma_{mu nu} (x) diag(1, -1, 0) at every site."""
+    import paper_1109_4279_amd as wc
+    from tests.test_oracle_operator import _flux_field, clover_flux_closed_form
+    dims, block, m0, csw = (8, 8, 4, 8), (4, 4, 2, 4), -0.1, 1.3
+    phi = 2 * np.pi * 3 / 8
+    for mu, nu in [(0, 1), (0, 3), (1, 3), (3, 2)]:
+        lat = wc.Lattice(to_dev(_flux_field(dims, mu, nu, phi)), block=block, m0=m0, csw=csw)
+        A = to_np(lat.clover())
+        want = clover_flux_closed_form(mu, nu, phi, m0, csw)
+        assert np.abs(A[..., 0, :, :] - want[:6, :6]).max() < 1e-14, (mu, nu)
+        assert np.abs(A[..., 1, :, :] - want[6:, 6:]).max() < 1e-14, (mu, nu)

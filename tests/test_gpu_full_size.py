@@ -73,8 +73,8 @@ def test_rhs_tile_autotuner_keeps_solutions():
     b = synth.point_sources(dims)
     kw = dict(nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec="f16", eo=1)
     x0, _ = lat.solve(to_dev(b), **kw)
-    nd, ns = lat.autotune(12, prec="f16")
-    assert nd in (1, 2, 4) and ns in (1, 2)
+    nd, nd64, ns, ne = lat.autotune(12, prec="f16")
+    assert nd in (1, 2, 4) and nd64 in (1, 2, 4) and ns in (1, 2) and ne in (1, 2)
     x1, st = lat.solve(to_dev(b), **kw)
     assert all(s["status"] == 0 for s in st)
     x1 = to_np(x1)
@@ -92,11 +92,41 @@ def test_fp64_dirac_tile_beyond_the_lds_stage():
     dims, block = (16, 8, 8, 8), (4, 4, 4, 4)
     lat = lattice(dims, block, M0, CSW)
     b = synth.gaussian_spinor(dims, nrhs=4, seed=61)
-    nd, ns = lat.autotune(4, prec="f64")
-    assert nd in (1, 2, 4) and ns == 1
+    nd, nd64, ns, ne = lat.autotune(4, prec="f64")
+    assert nd in (1, 2, 4) and nd == nd64 and ns == 1 and ne == 1
     x, st = lat.solve(to_dev(b), nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec="f64", nr_dirac=4)
     assert all(s["status"] == 0 for s in st)
     U, A = gauge(dims), clover(dims, M0, CSW)
     x = to_np(x)
     for r in (0, 3):
         assert _true_res(U, A, x[r], b[r]) <= 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_solves_32c64_checked_by_the_oracle():
+    """32^3 x 64 (Sec. 6's production lattice): the mixed solves on FP32, FP16 and BF16
+    storage and an independent FP64 reference (the plain MR block solver, tolerance 1e-12,
+    a different iteration from the mixed solves' even/odd block solver) all have their true
+    residual recomputed with the oracle's D over the whole lattice (time slabs); the mixed
+    solutions' error against the reference stays within the condition-number bound."""
+    from tests.helpers import oracle_true_res
+    dims, block = (64, 32, 32, 32), (4, 4, 4, 4)
+    lat = lattice(dims, block, M0, CSW)
+    U = gauge(dims)
+    b = synth.gaussian_spinor(dims)
+    xr, sr = lat.solve(to_dev(b), sap_prec="f64", eo=0, tol=1e-12)
+    assert sr[0]["status"] == 0
+    xs, st = [to_np(xr)], [sr[0]]
+    for sp in ("f32", "f16", "bf16"):
+        x, s = lat.solve(to_dev(b), sap_prec=sp, eo=1, tol=1e-10)
+        assert s[0]["status"] == 0
+        xs.append(to_np(x))
+        st.append(s[0])
+    res = oracle_true_res(U, M0, CSW, xs, [b] * len(xs), T=4, workers=8)
+    assert res[0] <= 1.01e-12
+    for r, s in zip(res, st):
+        assert r == pytest.approx(s["rel_true_res"], rel=1e-2)
+    for x, r in zip(xs[1:], res[1:]):
+        assert r <= 1e-10
+        # |x - x_ref| / |x_ref| <= cond(D) (tol + tol_ref), cond(D) ~ 1e2 for this operator
+        assert rel(x, xs[0]) < 2e-8

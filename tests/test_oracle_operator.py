@@ -211,3 +211,41 @@ def test_field_strength_constant_flux():
             for b in range(4):
                 if {a, b} != {mu, nu}:
                     assert np.abs(F[a, b]).max() < 1e-15
+
+
+def _flux_field(dims, mu, nu, phi):
+    """Unit links except U_nu(x) = diag(e^{i phi x_mu}, e^{-i phi x_mu}, 1): a constant abelian
+    flux phi through every (mu, nu) plaquette (L_mu phi must be a multiple of 2 pi)."""
+    x = dirac.coords(dims)
+    U = synth.unit_gauge(dims)
+    U[nu][..., 0, 0] = np.exp(1j * phi * x[..., mu])
+    U[nu][..., 1, 1] = np.exp(-1j * phi * x[..., mu])
+    return U
+
+
+def clover_flux_closed_form(mu, nu, phi, m0, csw):
+    """The clover term on a constant abelian flux in the (mu, nu) plane.  There F_{mu nu} =
+    i sin(phi) diag(1, -1, 0) and the other planes vanish (test_field_strength_constant_flux),
+    and sigma_{nu mu} F_{nu mu} = sigma_{mu nu} F_{mu nu}, so the sum over ordered pairs is
+    twice one term: A = (4 + m0) 1 + c_sw (i/2) sigma_{mu nu} (x) F_{mu nu}
+                      = (4 + m0) 1 - (c_sw / 2) sin(phi) sigma_{mu nu} (x) diag(1, -1, 0),
+    with sigma_{mu nu} = (i/2)[gamma_mu, gamma_nu] built from the (Clifford-pinned) gammas."""
+    from oracle.gamma import GAMMA
+    sig = 0.5j * (GAMMA[mu] @ GAMMA[nu] - GAMMA[nu] @ GAMMA[mu])
+    return (4 + m0) * np.eye(12) - 0.5 * csw * np.sin(phi) * np.kron(sig, np.diag([1.0, -1.0, 0.0]))
+
+
+def test_clover_constant_flux_closed_form():
+    """A constant abelian flux pins the clover coefficient c_sw (i/4), its sign and the factor
+    two of the ordered sum: A equals the closed form at every site, and (basis-free) its
+    spectrum is (4 + m0) +- (c_sw / 2) sin(phi), four times each, and (4 + m0) four times."""
+    dims, m0, csw = (8, 8, 4, 8), -0.1, 1.3
+    for mu, nu in [(0, 1), (0, 3), (1, 3), (3, 2)]:
+        phi = 2 * np.pi * 3 / 8
+        U = _flux_field(dims, mu, nu, phi)
+        A = dirac.clover_matrix(U, m0, csw)
+        want = clover_flux_closed_form(mu, nu, phi, m0, csw)
+        assert np.abs(A - want).max() < 1e-14, (mu, nu)
+        s = 0.5 * csw * np.sin(phi)
+        ev = np.sort(np.linalg.eigvalsh(A[0, 0, 0, 0]))
+        assert np.abs(ev - np.repeat([4 + m0 - s, 4 + m0, 4 + m0 + s], 4)).max() < 1e-14
