@@ -218,6 +218,20 @@ int wc_pseudofermion_action(wc_ctx* ctx, const void* phi, const wc_solver_params
  * derivative with respect to phi is 2 X).  out may equal in. */
 int wc_spinor_scale(wc_ctx* ctx, void* out, const void* in, int nrhs, double coef, void* stream);
 
+/* wc_apply_D without any device allocation, for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * layouts and results are those of wc_apply_D (same kernels, bit-identical output).  The
+ * packed input and output fields and the kernels' work list live in a fixed scratch array
+ * of 128 MiB per GPU that the library holds until the process ends; a call needs
+ * 256 B + 16 B per 256-site chunk and rhs tile + 2 x nrhs x V x (192 B FP64, 96 B FP32,
+ * 52 B 16-bit), e.g. 16^3 x 32 in FP64 up to 2 right-hand sides.  Larger requests return
+ * WC_ERR_ARG.  The operator must already be resident in prec (the FP64 one always is; any
+ * earlier wc_apply_D or solve in prec makes it so), else WC_ERR_STATE.  Every call on a GPU
+ * shares that GPU's scratch array, so calls that overlap on one GPU (other streams, other
+ * host threads, other contexts) race; nothing in the array needs clearing between calls. */
+int wc_apply_D_noalloc(wc_ctx* ctx, void* out, const void* in, int nrhs, int prec, int region, int dagger,
+                       void* stream);
+
 /* Harmonic Ritz pairs of an Arnoldi cycle (Sec. 4, the deflated restarts of FGMRES-DR),
  * computed on the host in FP64: eigenpairs of H + |h_{m+1,m}|^2 H^-H e_m e_m^T with H the
  * top m x m block of the (m+1) x m matrix Hbar.  Hbar: host complex128, column-major with

@@ -61,6 +61,7 @@ _SIGS = {
     "wc_set_block": (_I, [_P, ctypes.POINTER(_I), _P]),
     "wc_clover_export": (_I, [_P, _P, _P]),
     "wc_apply_D": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
+    "wc_apply_D_noalloc": (_I, [_P, _P, _P, _I, _I, _I, _I, _P]),
     "wc_harmonic_ritz": (_I, [_I, _P, _P, _P]),
     "wc_fgmres_dr_solve_batch": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                       ctypes.POINTER(_I), ctypes.POINTER(SolverParams), _I, ctypes.POINTER(SolverStats),

@@ -8,6 +8,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -168,6 +169,32 @@ struct Field {
 };
 
 struct Batch;
+
+// ---------------------------------------------------------------------------- allocation-free scratch
+
+// Device memory of wc_apply_D_noalloc: a fixed array in the library's code object, one copy
+// per GPU, held until the process ends.  Host code never names it in device work: it uses
+// the per-device address that scratch_setup() obtains from the runtime.
+constexpr size_t SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's scratch array (the device must be current); resolved once per
+// device, at the first context created on it.
+static void* scratch_setup(int dev) {
+  require(dev >= 0 && dev < SCRATCH_MAX_DEVICES, WC_ERR_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(ptr != nullptr, WC_ERR_HIP, "scratch array has no device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 }  // namespace wc
 
@@ -1247,6 +1274,7 @@ int wc_create_gauge(wc_ctx** ctx, const int dims[4], const int block[4], const v
     for (int m = 0; m < 4; ++m) require(dims[m] >= 2, WC_ERR_GEOMETRY, "lattice extents must be >= 2");
     auto c = std::make_unique<wc_ctx>();
     HIPCK(hipGetDevice(&c->dev));
+    scratch_setup(c->dev);
     for (int m = 0; m < 4; ++m) c->dims[m] = dims[m];
     c->bc_t = bc_t;
     const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
@@ -1310,6 +1338,101 @@ int wc_apply_D(wc_ctx* c, void* out, const void* in, int nrhs, int prec, int reg
     run_dirac(B, prec, pick_nr(c, nrhs, prec, false, 0), B.ain[prec], B.aout[prec], nullptr, nullptr, nullptr,
               dagger ? 1 : 0, region == WC_BLOCKS, st);
     unpack_batch(B, prec, B.aout[prec], outs, -1, st);
+    HIPCK(hipGetLastError());
+  });
+}
+
+}  // extern "C"
+
+namespace wc {
+
+// the lattice descriptor and the D work list of one lattice, written into scratch memory
+// (kernel arguments instead of a host copy, so that nothing is allocated or staged)
+__global__ void k_noalloc_tables(LatDesc L, int nrhs, int nr, LatDesc* lat_out, WorkItem* items) {
+  const int nch = L.nchunks;
+  const int ngroups = (nrhs + nr - 1) / nr;
+  const int n = nch * ngroups;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int grp = i / nch, chunk = i - grp * nch;
+    const int r0 = grp * nr;
+    items[i] = WorkItem{0, chunk, r0, min(nr, nrhs - r0)};
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *lat_out = L;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace wc
+
+extern "C" {
+
+int wc_apply_D_noalloc(wc_ctx* c, void* out, const void* in, int nrhs, int prec, int region, int dagger,
+                       void* stream) {
+  return guarded([&] {
+    require(c && out && in && nrhs >= 1, WC_ERR_ARG, "null argument or nrhs < 1");
+    check_prec(prec);
+    require(region == WC_FULL || region == WC_BLOCKS, WC_ERR_ARG, "bad region");
+    require(c->have_clover, WC_ERR_STATE, "clover term not created");
+    require(c->have_links[prec] && c->have_clov[prec], WC_ERR_STATE,
+            "the operator is not resident in this precision: call wc_apply_D once in it first");
+    static_assert(sizeof(LatDesc) <= 256, "lattice descriptor exceeds its scratch slot");
+    const Geom& g = c->g;
+    const int nr = pick_nr(c, nrhs, prec, false, 0);
+    const int nch = (g.V + WG - 1) / WG;
+    const long long nitems = (long long)nch * ((nrhs + nr - 1) / nr);
+    const size_t field = align256(spinor_bytes(prec, (long long)nrhs * g.V));
+    const size_t scales = is16(prec) ? align256(sizeof(float) * (size_t)nrhs * g.V) : 0;
+    const size_t items_off = 256, in_off = items_off + align256(sizeof(WorkItem) * (size_t)nitems);
+    const size_t out_off = in_off + field + scales, need = out_off + field + scales;
+    require(need <= SCRATCH_BYTES, WC_ERR_ARG,
+            "wc_apply_D_noalloc: " + std::to_string(need >> 20) + " MiB of scratch needed for this lattice, nrhs " +
+                "and precision; the limit is " + std::to_string(SCRATCH_BYTES >> 20) + " MiB");
+    char* base = (char*)scratch_setup(c->dev);
+    hipStream_t st = S(stream);
+    LatDesc L;
+    std::memset(&L, 0, sizeof L);
+    L.g = g;
+    L.gauge = c->links[prec].p;
+    L.gscale = c->lscale[prec].as<float>();
+    L.clov = c->clov[prec].p;
+    L.cscale = c->cscale[prec].as<float>();
+    L.foff = 0;
+    L.nrhs = nrhs;
+    L.nchunks = nch;
+    L.tiles[0] = c->tiles[0].as<int>();
+    L.tiles[1] = c->tiles[1].as<int>();
+    L.eo_sites = c->eo_sites.as<short>();
+    L.eo_slot = c->eo_slot.as<short>();
+    LatDesc* d_lat = (LatDesc*)base;
+    WorkItem* d_items = (WorkItem*)(base + items_off);
+    hipLaunchKernelGGL(k_noalloc_tables, dim3((unsigned)std::min<long long>((nitems + 255) / 256, 1024)), dim3(256), 0,
+                       st, L, nrhs, nr, d_lat, d_items);
+    void* fin = base + in_off;
+    float* fin_sc = scales ? (float*)(base + in_off + field) : nullptr;
+    void* fout = base + out_off;
+    float* fout_sc = scales ? (float*)(base + out_off + field) : nullptr;
+    launch_pack_spinor(prec, g, nrhs, in, fin, fin_sc, st);
+    DiracLaunch a;
+    a.lats = d_lat;
+    a.items = d_items;
+    a.nitems = (int)nitems;
+    a.in = fin;
+    a.in_sc = fin_sc;
+    a.out = fout;
+    a.out_sc = fout_sc;
+    a.y = nullptr;
+    a.y_sc = nullptr;
+    a.partials = nullptr;
+    a.pw = 0;
+    a.skip = nullptr;
+    a.dagger = dagger ? 1 : 0;
+    a.block = region == WC_BLOCKS;
+    // the staging rule of wc_apply_D (a single lattice: its tiles decide)
+    const int forced = c->opt_dirac_stage;
+    const int stage = g.bvol != 256 ? 0 : (forced >= 0 ? forced : (prec == P_F64 ? 1 : 0));
+    a.stage = stage && dirac_stage_lds_bytes(prec, nr) <= LDS_MAX_BYTES;
+    launch_dirac(prec, nr, a, persistent_grid(a.nitems, 8), st);
+    launch_unpack_spinor(prec, g, nrhs, fout, fout_sc, out, -1, st);
     HIPCK(hipGetLastError());
   });
 }
