@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/wc.h"
+#include "wc.h"
 #include "dense_host.h"
 #include "wc_kernels.h"
 
@@ -506,7 +506,12 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
                               const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st,
                               int odd_rho = 0) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
-  require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
+  // the even/odd solver's border update runs from LDS entries when they fit a work-group's
+  // LDS next to the exchange rows (else per site)
+  int bentries = 0;
+  for (auto* c : B.lat) bentries = std::max(bentries, border_entry_count(c->g.B));
+  if (eo && sap_eo_lds_bytes(prec, nr, B.max_bvol, bentries) > LDS_MAX_BYTES) bentries = 0;
+  require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol, 0) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
   const LatDesc* L = B.lats(prec, st, eo != 0);
   const ItemList& it = B.items_sap(colour, nr);
@@ -530,6 +535,10 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
   a.cache = sap_cache_mode(B, it.n);
   a.uniform_bvol = B.uniform_bvol;
   a.odd_rho = odd_rho;
+  // (with the operator cached the launch has one work-group per CU, and the entries'
+  // extra barrier costs more than the divergent per-site update: measured at 16^3 x 32)
+  a.border_entries = (eo && !a.cache) ? bentries : 0;
+  a.eo_rows = 2 * ((B.max_bvol + 1) / 2);
   if (eo)
     launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), B.max_bvol, st);
   else if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
@@ -1773,7 +1782,7 @@ int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[4], void* stream) {
   return guarded([&] {
     require(c && nrhs >= 1, WC_ERR_ARG, "bad argument");
     check_prec(prec);
-    const int cands[3] = {1, 2, 4};
+    const int cands[4] = {1, 2, 3, 4};
     // D tiles: in prec and, for the outer solver, in FP64
     std::vector<int> dps = {prec};
     if (prec != P_F64) dps.push_back(P_F64);

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(WG) void k_pack_links(Geom g, const double2* canon,
       uint32_t w[9];
       for (int k = 0; k < 9; ++k) {
         double2 v = canon[((size_t)mu * V + x) * 9 + k];
-        w[k] = uint32_t(f32_to_s16<P>(float(v.x) * inv)) | (uint32_t(f32_to_s16<P>(float(v.y) * inv)) << 16);
+        w[k] = f32x2_to_s16x2<P>(float(v.x) * inv, float(v.y) * inv);
       }
       d4[((size_t)mu * 2) * V + s] = make_uint4(w[0], w[1], w[2], w[3]);
       d4[((size_t)mu * 2 + 1) * V + s] = make_uint4(w[4], w[5], w[6], w[7]);
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(WG) void k_clover_convert(Geom g, const double2* c6
       uint32_t w[4];
       for (int j = 0; j < 4; ++j) {
         int i0 = 8 * k + 2 * j, i1 = i0 + 1;
-        w[j] = uint32_t(f32_to_s16<P>(r[i0] / sc[i0 / 36])) | (uint32_t(f32_to_s16<P>(r[i1] / sc[i1 / 36])) << 16);
+        w[j] = f32x2_to_s16x2<P>(r[i0] / sc[i0 / 36], r[i1] / sc[i1 / 36]);
       }
       d[(size_t)k * g.V + s] = make_uint4(w[0], w[1], w[2], w[3]);
     }

@@ -24,32 +24,44 @@ WC_D Herm6<R> clover_block(const LatDesc& L, int V, int site, int blk) {
     return CloverIO<P>::load_raw(L.clov_eo, L.cscale_eo, V, site, blk);
   } else {
     // 72 halves per site in 9 uint4; block 0 is halves 0..35 of uint4 0..4, block 1 is
-    // halves 4..39 of uint4 4..8: load five uint4 from 4*blk and pick with a select
+    // halves 4..39 of uint4 4..8: load five uint4 from 4*blk and take the block's 18 words
+    // (a word-level select: block 1 starts two words in)
     const size_t p = (size_t)site + (size_t)(4 * blk) * V;
-    float H[40];
+    uint32_t wd[20];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      uint4 v = gld_u4(L.clov_eo, p + (size_t)k * V);
-      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      const uint4 v = gld_u4(L.clov_eo, p + (size_t)k * V);
+      wd[4 * k] = v.x;
+      wd[4 * k + 1] = v.y;
+      wd[4 * k + 2] = v.z;
+      wd[4 * k + 3] = v.w;
+    }
+    float H[36];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        H[8 * k + 2 * j] = s16_to_f32<P>(uint16_t(w[j] & 0xFFFFu));
-        H[8 * k + 2 * j + 1] = s16_to_f32<P>(uint16_t(w[j] >> 16));
-      }
+    for (int j = 0; j < 18; ++j) {
+      const uint32_t u = blk ? wd[j + 2] : wd[j];
+      H[2 * j] = s16_to_f32<P>(uint16_t(u & 0xFFFFu));
+      H[2 * j + 1] = s16_to_f32<P>(uint16_t(u >> 16));
     }
     Herm6<R> h;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) h.d[i] = blk ? H[i + 4] : H[i];
+    for (int i = 0; i < 6; ++i) h.d[i] = H[i];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) h.o[k] = {blk ? H[10 + 2 * k] : H[6 + 2 * k], blk ? H[11 + 2 * k] : H[7 + 2 * k]};
+    for (int k = 0; k < 15; ++k) h.o[k] = {H[6 + 2 * k], H[7 + 2 * k]};
     return h;
   }
+}
+
+// the storage scale of clover block blk (1 for FP64 / FP32 storage)
+template <int P, class R>
+WC_D R clover_scale(const LatDesc& L, int site, int blk) {
+  return CloverIO<P>::scale(L.cscale_eo, site, blk);
 }
 
 template <int P, class R>
 WC_D Herm6<R> clover_block_scaled(const LatDesc& L, int V, int site, int blk) {
   Herm6<R> h = clover_block<P, R>(L, V, site, blk);
-  const R cs = CloverIO<P>::scale(L.cscale_eo, site, blk);
+  const R cs = clover_scale<P, R>(L, site, blk);
   if (P == P_F16 || P == P_BF16) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) h.d[i] *= cs;

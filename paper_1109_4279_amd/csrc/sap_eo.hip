@@ -34,52 +34,50 @@ namespace wc {
 
 constexpr int EO_MAX_WAVES = 4;  // blocks of at most 256 sites: 128 pairs, 256 lanes
 
-// acc += w * (1 + SGN gamma_mu)-hop of the transported neighbour spinor p, for mu = 2s + J.
-// J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.
+// acc += w * (1 + SGN gamma_mu)-hop of a transported neighbour spinor, for mu = 2s + J.
+// J = 0: mu = 0 or 2;  J = 1: mu = 1 or 3.  In the chiral basis the projection is
+//   J = 0: mu = 0: h = u - SGN (l0, l1);        mu = 2: h = u - SGN (l1, -l0)
+//   J = 1: mu = 1: h = u - SGN i (l1, l0);      mu = 3: h = u - SGN i (l0, -l1)
+// so with lA, lB the lower spins in the lane's order (J = 0: lA = l_{2+s}, lB = l_{3-s};
+// J = 1: lA = l_{3-s}, lB = l_{2+s}; read from LDS at lane-dependent rows) and the lane sign
+// sg = +1 (s = 0), -1 (s = 1), h0 = u0 - SGN phase lA and h1 = u1 - SGN phase sg lB, phase 1
+// or i.  The reconstruction adds t = w U h to the upper spins and, to the lower pair kept in
+// the lane's order (L0, L1) = (acc2, acc3) for s = 0 and (acc3, acc2) for s = 1,
+//   J = 0: L0 += -SGN t0,      L1 += -SGN sg t1
+//   J = 1: L0 += SGN sg i t1,  L1 += SGN i t0.
+// The lane sign enters as a per-lane coefficient of a fused multiply-add: no selects.
 template <class R, int J, int SGN, bool DAG>
-WC_D void hop_dir(const SU3<R>& U, const Spinor<R>& p, int s, R w, Spinor<R>& acc) {
+WC_D void hop_dir(const SU3<R>& U, const cplx<R>* u0, const cplx<R>* u1, const cplx<R>* lA, const cplx<R>* lB,
+                  R sg, R w, Spinor<R>& acc) {
+  constexpr R S = R(SGN);
+  const R c1 = -S * sg;  // J = 0: h1 = u1 + c1 lB;  J = 1: h1 = u1 - c1 i lB
   Half<R> h;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cplx<R> u0 = p.c[0][a], u1 = p.c[1][a], l0 = p.c[2][a], l1 = p.c[3][a];
-    // J = 0: mu = 0: h = u - SGN (l0, l1);        mu = 2: h = u - SGN (l1, -l0)
-    // J = 1: mu = 1: h = u - SGN i (l1, l0);      mu = 3: h = u - SGN i (l0, -l1)
-    // the lane sign (+1 for s = 0, -1 for s = 1) enters as a negated select
-    cplx<R> x0, x1;
     if (J == 0) {
-      x0 = s ? l1 : l0;
-      x1 = s ? -l0 : l1;
+      h.c[0][a] = {u0[a].re - S * lA[a].re, u0[a].im - S * lA[a].im};
+      h.c[1][a] = {fma(c1, lB[a].re, u1[a].re), fma(c1, lB[a].im, u1[a].im)};
     } else {
-      x0 = s ? l0 : l1;
-      x1 = s ? -l1 : l0;
-    }
-    if (J == 0) {
-      h.c[0][a] = SGN > 0 ? u0 - x0 : u0 + x0;
-      h.c[1][a] = SGN > 0 ? u1 - x1 : u1 + x1;
-    } else {
-      h.c[0][a] = SGN > 0 ? u0 - timesI(x0) : u0 + timesI(x0);
-      h.c[1][a] = SGN > 0 ? u1 - timesI(x1) : u1 + timesI(x1);
+      h.c[0][a] = {u0[a].re + S * lA[a].im, u0[a].im - S * lA[a].re};
+      h.c[1][a] = {fma(-c1, lB[a].im, u1[a].re), fma(c1, lB[a].re, u1[a].im)};
     }
   }
   const Half<R> t = DAG ? mul_Udag(U, h) : mul_U(U, h);
+  // J = 0: L0 += wl0 t0, L1 += wl1 t1;  J = 1: L0 += -wl0 i t1, L1 += wl1 i t0
+  const R wl0 = J == 0 ? -S * w : -S * sg * w;
+  const R wl1 = J == 0 ? -S * sg * w : S * w;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cplx<R> t0 = w * t.c[0][a], t1 = w * t.c[1][a];
-    acc.c[0][a] = acc.c[0][a] + t0;
-    acc.c[1][a] = acc.c[1][a] + t1;
-    // J = 0: mu = 0: lower += -SGN (t0, t1);      mu = 2: lower += -SGN (-t1, t0)
-    // J = 1: mu = 1: lower += SGN i (t1, t0);     mu = 3: lower += SGN i (t0, -t1)
-    cplx<R> y0, y1;
+    const cplx<R> t0 = t.c[0][a], t1 = t.c[1][a];
+    acc.c[0][a] = {fma(w, t0.re, acc.c[0][a].re), fma(w, t0.im, acc.c[0][a].im)};
+    acc.c[1][a] = {fma(w, t1.re, acc.c[1][a].re), fma(w, t1.im, acc.c[1][a].im)};
     if (J == 0) {
-      y0 = s ? -t1 : t0;
-      y1 = s ? t0 : t1;
-      acc.c[2][a] = SGN > 0 ? acc.c[2][a] - y0 : acc.c[2][a] + y0;
-      acc.c[3][a] = SGN > 0 ? acc.c[3][a] - y1 : acc.c[3][a] + y1;
+      acc.c[2][a] = {fma(wl0, t0.re, acc.c[2][a].re), fma(wl0, t0.im, acc.c[2][a].im)};
+      acc.c[3][a] = {fma(wl1, t1.re, acc.c[3][a].re), fma(wl1, t1.im, acc.c[3][a].im)};
     } else {
-      y0 = s ? t0 : t1;
-      y1 = s ? -t1 : t0;
-      acc.c[2][a] = SGN > 0 ? acc.c[2][a] + timesI(y0) : acc.c[2][a] - timesI(y0);
-      acc.c[3][a] = SGN > 0 ? acc.c[3][a] + timesI(y1) : acc.c[3][a] - timesI(y1);
+      // L0 += S sg w i t1 = (-S sg w t1.im, S sg w t1.re);  L1 += S w i t0 = (-S w t0.im, S w t0.re)
+      acc.c[2][a] = {fma(wl0, t1.im, acc.c[2][a].re), fma(-wl0, t1.re, acc.c[2][a].im)};
+      acc.c[3][a] = {fma(-wl1, t0.im, acc.c[3][a].re), fma(wl1, t0.re, acc.c[3][a].im)};
     }
   }
 }
@@ -136,26 +134,40 @@ WC_D void lds_spinor(const cplx<R>* lds, int ls, int r, int slot, Spinor<R>& p) 
 }
 
 // out[r] = chirality block s of wt * (sum of this pair's in-block hops at site x), read from
-// LDS.  Every lane of the wavefront must call this (it shuffles).
+// LDS.  Every lane of the wavefront must call this (it shuffles).  The lower spins of the
+// accumulator are kept in the lane's order (hop_dir), resolved once in the final exchange.
 template <int P, int NR, bool CACHE, class R>
 WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x, bool act, const cplx<R>* lds,
                     int ls, int s, R wt, cplx<R> (*out)[6]) {
   Spinor<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) zero(acc[r]);
+  const R sg = s ? R(-1) : R(1);
   if (act) {
     const int base = x.site - x.local;
     auto dir = [&](auto Jc) {
       constexpr int J = decltype(Jc)::value;
       const int mu = 2 * s + J;
+      // rows of the lower spins in the lane's order
+      const int rowA = 3 * (J == 0 ? 2 + s : 3 - s), rowB = 3 * (J == 0 ? 3 - s : 2 + s);
+      auto read = [&](int r, int slot, cplx<R>* u0, cplx<R>* u1, cplx<R>* lA, cplx<R>* lB) {
+        const cplx<R>* q = lds + (size_t)(r * 12) * ls + slot;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          u0[a] = q[a * ls];
+          u1[a] = q[(3 + a) * ls];
+          lA[a] = q[(rowA + a) * ls];
+          lB[a] = q[(rowB + a) * ls];
+        }
+      };
       if (x.f[J]) {
         const SU3<R> U = CACHE ? x.Uf[CACHE ? J : 0] : LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, mu, x.site);
         const R w = CACHE ? wt : wt * LinkIO<P>::scale(L.gscale, x.site);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p;
-          lds_spinor<NR>(lds, ls, r, x.snf[J], p);
-          hop_dir<R, J, -1, false>(U, p, s, w, acc[r]);
+          cplx<R> u0[3], u1[3], lA[3], lB[3];
+          read(r, x.snf[J], u0, u1, lA, lB);
+          hop_dir<R, J, -1, false>(U, u0, u1, lA, lB, sg, w, acc[r]);
         }
       }
       if (x.b[J]) {
@@ -164,36 +176,46 @@ WC_D void pair_hops(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x
         const R w = CACHE ? wt : wt * LinkIO<P>::scale(L.gscale, nb);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Spinor<R> p;
-          lds_spinor<NR>(lds, ls, r, x.snb[J], p);
-          hop_dir<R, J, +1, true>(U, p, s, w, acc[r]);
+          cplx<R> u0[3], u1[3], lA[3], lB[3];
+          read(r, x.snb[J], u0, u1, lA, lB);
+          hop_dir<R, J, +1, true>(U, u0, u1, lA, lB, sg, w, acc[r]);
         }
       }
     };
     dir(std::integral_constant<int, 0>());
     dir(std::integral_constant<int, 1>());
   }
+  // lane 0 keeps the upper spins and sends its lower pair (acc2, acc3); lane 1 keeps its
+  // lower pair, stored as (acc3, acc2), and sends its upper spins
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      const cplx<R> mine = s ? acc[r].c[2 + i / 3][i % 3] : acc[r].c[i / 3][i % 3];
-      const cplx<R> other = s ? acc[r].c[i / 3][i % 3] : acc[r].c[2 + i / 3][i % 3];
-      out[r][i] = mine + shfl1(other);
+      const cplx<R> up = acc[r].c[i / 3][i % 3];
+      const cplx<R> low = acc[r].c[2 + i / 3][i % 3];
+      const cplx<R> low_sw = acc[r].c[2 + (1 - i / 3)][i % 3];
+      const cplx<R> mine = s ? low_sw : up;
+      const cplx<R> send = s ? up : low;
+      out[r][i] = mine + shfl1(send);
     }
 }
 
-// out[r] (+)= C_s(x) in[r] on chirality block s
+// out[r] (+)= C_s(x) in[r] on chirality block s (a 16-bit block's scale multiplies the
+// product, six complex numbers, rather than the block's 36 entries)
 template <int P, int NR, bool CACHE, bool ACC, class R>
 WC_D void clover_half(const LatDesc& L, const Geom& g, const LaneSite<R, CACHE>& x, int s, const cplx<R> (*in)[6],
                       cplx<R> (*out)[6]) {
-  const Herm6<R> h = CACHE ? x.C[0] : clover_block_scaled<P, R>(L, g.V, x.site, s);
+  const Herm6<R> h = CACHE ? x.C[0] : clover_block<P, R>(L, g.V, x.site, s);
+  const R cs = CACHE ? R(1) : clover_scale<P, R>(L, x.site, s);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     cplx<R> o[6];
     herm6_apply(h, in[r], o);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) out[r][i] = ACC ? out[r][i] + o[i] : o[i];
+    for (int i = 0; i < 6; ++i) {
+      if (!CACHE && (P == P_F16 || P == P_BF16)) o[i] = cs * o[i];
+      out[r][i] = ACC ? out[r][i] + o[i] : o[i];
+    }
   }
 }
 
@@ -241,12 +263,127 @@ WC_D void border_update(const LatDesc& L, const Geom& g, int site, int tile, con
   one(std::integral_constant<int, 3>());
 }
 
+// The border update as entries: every hop out of the block (direction mu, forward or
+// backward face, face site f) is one entry, ordered by direction, forward face before
+// backward, face sites lexicographic in the other three coordinates (x3 fastest).  The
+// entries of one face share the direction, so a wavefront of them runs one code path; each
+// writes the hop's contribution to rho (+1/2 (1 -+ gamma_mu) U z of the neighbouring block)
+// to its own LDS slot, and the sites then add their entries (none inside the block, up to
+// one per face they lie on).
+WC_HD int face_size(const Geom& g, int mu) { return g.bvol / g.B[mu]; }
+
+WC_D int face_index(const Geom& g, const int* lc, int mu) {
+  int f = 0;
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu)
+    if (nu != mu) f = f * g.B[nu] + lc[nu];
+  return f;
+}
+
+template <int P, int NR, int MU, class R>
+WC_D void border_entry(const LatDesc& L, const Geom& g, int tile, const int* tc, int base, int f, bool fwd,
+                       const FieldRef* fz, cplx<R>* bord, int ne, int e) {
+  int lc[4];
+  int q = f;
+#pragma unroll
+  for (int nu = 3; nu >= 0; --nu) {
+    if (nu == MU) continue;
+    lc[nu] = q % g.B[nu];
+    q /= g.B[nu];
+  }
+  lc[MU] = fwd ? g.B[MU] - 1 : 0;
+  const int local = lc[0] * g.lstr[0] + lc[1] * g.lstr[1] + lc[2] * g.lstr[2] + lc[3] * g.lstr[3];
+  const int site = base + local;
+  Spinor<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) zero(acc[r]);
+  int ph;
+  bool inside;
+  if (fwd) {
+    const int nf = neighbour(g, site, tile, tc, lc, MU, +1, &ph, &inside);
+    const SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, site);
+    const R w = R(0.5) * R(ph) * LinkIO<P>::scale(L.gscale, site);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const Spinor<R> p = SpinorIO<P>::load_raw(fz[r], nf);
+      accum_recon<R, MU, -1>(acc[r], mul_U(u, project<R, MU, -1>(p)), w * SpinorIO<P>::scale(fz[r], nf));
+    }
+  } else {
+    const int nb = neighbour(g, site, tile, tc, lc, MU, -1, &ph, &inside);
+    const SU3<R> u = LinkIO<P>::load_raw(L.gauge, L.gscale, g.V, MU, nb);
+    const R w = R(0.5) * R(ph) * LinkIO<P>::scale(L.gscale, nb);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const Spinor<R> p = SpinorIO<P>::load_raw(fz[r], nb);
+      accum_recon<R, MU, +1>(acc[r], mul_Udag(u, project<R, MU, +1>(p)), w * SpinorIO<P>::scale(fz[r], nb));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) bord[(r * 12 + k) * ne + e] = acc[r].c[k / 3][k % 3];
+}
+
+// all entries of the block into LDS; the caller puts a barrier after it
+template <int P, int NR, class R>
+WC_D void border_entries(const LatDesc& L, const Geom& g, int tile, const int* tc, int base, const FieldRef* fz,
+                         cplx<R>* bord, int ne) {
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    int off = 0, mu = 3, f = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int n2 = 2 * face_size(g, m);
+      if (e - off < n2) {
+        mu = m;
+        break;
+      }
+      off += n2;
+    }
+    f = e - off;
+    const int F = face_size(g, mu);
+    const bool fwd = f < F;
+    if (!fwd) f -= F;
+    switch (mu) {
+      case 0: border_entry<P, NR, 0>(L, g, tile, tc, base, f, fwd, fz, bord, ne, e); break;
+      case 1: border_entry<P, NR, 1>(L, g, tile, tc, base, f, fwd, fz, bord, ne, e); break;
+      case 2: border_entry<P, NR, 2>(L, g, tile, tc, base, f, fwd, fz, bord, ne, e); break;
+      default: border_entry<P, NR, 3>(L, g, tile, tc, base, f, fwd, fz, bord, ne, e); break;
+    }
+  }
+}
+
+// rho(site) += its border entries (site with tile-local coordinates lc)
+template <int NR, class R>
+WC_D void border_gather(const Geom& g, const int* lc, const cplx<R>* bord, int ne, Spinor<R>* rho) {
+  int off = 0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int F = face_size(g, mu);
+    const int f = face_index(g, lc, mu);
+    if (lc[mu] == g.B[mu] - 1) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) rho[r].c[k / 3][k % 3] = rho[r].c[k / 3][k % 3] + bord[(r * 12 + k) * ne + off + f];
+    }
+    if (lc[mu] == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+          rho[r].c[k / 3][k % 3] = rho[r].c[k / 3][k % 3] + bord[(r * 12 + k) * ne + off + F + f];
+    }
+    off += 2 * F;
+  }
+}
+
 template <int P, int NR, bool CACHE>
 __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
   typedef typename Real<P>::T R;
   extern __shared__ double smem_d[];
   double* red = smem_d;                                        // EO_MAX_WAVES * 3 * NR doubles
   cplx<R>* lds = (cplx<R>*)(smem_d + EO_MAX_WAVES * 3 * NR);  // [NR][12][bvol]
+  cplx<R>* bord = lds + (size_t)NR * 12 * a.eo_rows;           // [NR][12][border entries]
 
   const int s = threadIdx.x & 1;
   const int pr = threadIdx.x >> 1;
@@ -306,7 +443,14 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
         else
           v[r] = SpinorIO<P>::load(frho[r], own);
       }
-      if (a.border && own_act) border_update<P, NR>(L, g, own, tile, tc, s ? lco : lce, fz, v);
+      if (a.border && a.border_entries) {
+        const int ne = border_entry_count(g.B);
+        border_entries<P, NR>(L, g, tile, tc, base, fz, bord, ne);
+        __syncthreads();
+        if (own_act) border_gather<NR>(g, s ? lco : lce, bord, ne, v);
+      } else if (a.border && own_act) {
+        border_update<P, NR>(L, g, own, tile, tc, s ? lco : lce, fz, v);
+      }
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -442,9 +586,10 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
 
 static int eo_threads(int max_bvol) { return (2 * ((max_bvol + 1) / 2) + 63) / 64 * 64; }
 
-size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol) {
+size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol, int border_entries) {
   const size_t cb = prec == P_F64 ? 16 : 8;
-  return sizeof(double) * EO_MAX_WAVES * 3 * nr + cb * 12 * (size_t)nr * (2 * ((max_bvol + 1) / 2));
+  return sizeof(double) * EO_MAX_WAVES * 3 * nr + cb * 12 * (size_t)nr * (2 * ((max_bvol + 1) / 2)) +
+         cb * 12 * (size_t)nr * border_entries;
 }
 
 template <int P>
@@ -463,7 +608,7 @@ static void launch_p(const SapLaunch& a, int nr, int grid, int threads, size_t l
 }
 
 void launch_sap_eo(int prec, int nr, const SapLaunch& a, int grid, int max_bvol, hipStream_t st) {
-  const size_t lds = sap_eo_lds_bytes(prec, nr, max_bvol);
+  const size_t lds = sap_eo_lds_bytes(prec, nr, max_bvol, a.border_entries);
   const int threads = eo_threads(max_bvol);
   switch (prec) {
     case P_F64: launch_p<P_F64>(a, nr, grid, threads, lds, st); break;

@@ -264,6 +264,19 @@ template <int P> WC_D uint16_t f32_to_s16(float f) {
   if (P == P_BF16) return f32_to_bf16(f);
   return f32_to_h16(f);
 }
+// Two values to packed 16-bit storage, a in the low half, rounded to nearest even: one
+// v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32 on gfx950 (the same rounding as f32_to_s16).
+template <int P> WC_D uint32_t f32x2_to_s16x2(float a, float b) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v v = {a, b};
+  if constexpr (P == P_BF16) {
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2v));
+  } else {
+    typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2v));
+  }
+}
 
 // compute type per storage precision
 template <int P> struct Real { typedef float T; };

@@ -187,8 +187,7 @@ template <int P> struct SpinorIO16 {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         int c = 4 * k + j;
-        w[j] = uint32_t(f32_to_s16<P>(o.c[c / 3][c % 3].re * inv)) |
-               (uint32_t(f32_to_s16<P>(o.c[c / 3][c % 3].im * inv)) << 16);
+        w[j] = f32x2_to_s16x2<P>(o.c[c / 3][c % 3].re * inv, o.c[c / 3][c % 3].im * inv);
       }
       p[(size_t)k * f.V] = make_uint4(w[0], w[1], w[2], w[3]);
     }

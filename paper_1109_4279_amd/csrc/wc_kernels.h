@@ -50,6 +50,11 @@ struct SapLaunch {
   // even/odd solver, residual on odd sites (zero after every solve of the block):
   // 0 read and stored, 1 read but not stored, 2 neither read (taken as zero) nor stored
   int odd_rho;
+  // even/odd solver: the border update's cross-block hops as LDS entries (border_entries =
+  // the largest count of any lattice of the launch; 0 = per-site path), after the exchange
+  // rows of length eo_rows
+  int border_entries;
+  int eo_rows;
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
@@ -58,7 +63,14 @@ void launch_sap_mr_lds(int prec, int nr, const SapLaunch& a, int grid, hipStream
 
 // even/odd-preconditioned block solver: two lanes per (even site, odd site) pair of a block
 void launch_sap_eo(int prec, int nr, const SapLaunch& a, int grid, int max_bvol, hipStream_t st);
-size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol);
+// dynamic LDS of the even/odd solver: reduction scratch, the exchange rows and, when
+// border_entries > 0, the border update's entries
+size_t sap_eo_lds_bytes(int prec, int nr, int max_bvol, int border_entries);
+// cross-block hops of one block (the border update's entries): two faces per direction
+WC_HD int border_entry_count(const int* B) {
+  const int vol = B[0] * B[1] * B[2] * B[3];
+  return 2 * (vol / B[0] + vol / B[1] + vol / B[2] + vol / B[3]);
+}
 
 // ----------------------------------------------------------------- layout conversion / setup
 // canonical complex128 [rhs][V][4][3] (lexicographic) <-> internal field of one lattice
