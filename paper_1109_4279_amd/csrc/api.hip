@@ -292,6 +292,9 @@ struct Batch {
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
   DevBuf d_chi, d_phi;
+  // FGCR directions in the preconditioner's storage, and their pointer tables
+  Field dir[NKV_MAX];
+  DevBuf d_dir, d_dir_sc;
   Field sap_rho, sap_z, sap_psi;
   DevBuf sys, skip;
   DevBuf hist;  // [nsys][HIST_MAX] relative true residual after each restart
@@ -477,6 +480,7 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   a.nitems = it.n;
   a.in = in.data();
   a.in_sc = in.scale();
+  a.in_prec = in.prec;
   a.out = out.data();
   a.out_sc = out.scale();
   a.y = y ? y->data() : nullptr;
@@ -650,25 +654,43 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.sp = nullptr;
   a.sp_sc = nullptr;
   a.arn = nullptr;
+  a.dir = B.d_dir.as<void* const>();
+  a.dir_sc = B.d_dir_sc.as<float* const>();
+  a.dir_prec = s.sap_prec;
+  a.fuse_sap = 0;
   return a;
 }
 
-static void prepare_solver(Batch& B, const SolveSetup& s) {
+// fgcr: the directions live in the preconditioner's storage (dir); FGMRES-DR keeps its
+// preconditioned basis Z in FP64 (phi), which its deflated restarts recombine
+static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   const long long n = B.sites_rhs;
   B.x.ensure(P_F64, n);
   B.b.ensure(P_F64, n);
   B.r.ensure(P_F64, n);
   std::vector<double2*> pc(NKV_MAX, nullptr), pp(NKV_MAX, nullptr);
+  std::vector<void*> pd(NKV_MAX, nullptr);
+  std::vector<float*> pds(NKV_MAX, nullptr);
   for (int k = 0; k < s.nkv; ++k) {
     B.chi[k].ensure(P_F64, n);
-    B.phi[k].ensure(P_F64, n);
     pc[k] = B.chi[k].d.as<double2>();
-    pp[k] = B.phi[k].d.as<double2>();
+    if (fgcr) {
+      B.dir[k].ensure(s.sap_prec, n);
+      pd[k] = B.dir[k].data();
+      pds[k] = B.dir[k].scale();
+    } else {
+      B.phi[k].ensure(P_F64, n);
+      pp[k] = B.phi[k].d.as<double2>();
+    }
   }
   B.d_chi.ensure(sizeof(double2*) * NKV_MAX);
   B.d_phi.ensure(sizeof(double2*) * NKV_MAX);
+  B.d_dir.ensure(sizeof(void*) * NKV_MAX);
+  B.d_dir_sc.ensure(sizeof(float*) * NKV_MAX);
   HIPCK(hipMemcpy(B.d_chi.p, pc.data(), sizeof(double2*) * NKV_MAX, hipMemcpyHostToDevice));
   HIPCK(hipMemcpy(B.d_phi.p, pp.data(), sizeof(double2*) * NKV_MAX, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(B.d_dir.p, pd.data(), sizeof(void*) * NKV_MAX, hipMemcpyHostToDevice));
+  HIPCK(hipMemcpy(B.d_dir_sc.p, pds.data(), sizeof(float*) * NKV_MAX, hipMemcpyHostToDevice));
   B.sap_rho.ensure(s.sap_prec, n);
   B.sap_z.ensure(s.sap_prec, n);
   B.sap_psi.ensure(s.sap_prec, n);
@@ -693,32 +715,37 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
   mark(tm, PH_BLAS, st);
   for (int k = 0; k < s.nkv; ++k) {
     va.k = k;
-    // phi_k = |r| M_SAP(r / |r|)
-    VecLaunch vs = va;
-    vs.sp = B.sap_rho.data();
-    vs.sp_sc = B.sap_rho.scale();
-    launch_to_sap(s.sap_prec, vs, gv, st);
-    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.sap_psi, skip, s.eo, st);
-    vs.sp = B.sap_psi.data();
-    vs.sp_sc = B.sap_psi.scale();
-    launch_from_sap(s.sap_prec, vs, gv, st);
+    // phi_k = M_SAP(r / |r_k|) as the preconditioner stores it (the input of step k > 0 was
+    // written by step k - 1's residual update)
+    if (k == 0) {
+      VecLaunch vs = va;
+      vs.sp = B.sap_rho.data();
+      vs.sp_sc = B.sap_rho.scale();
+      launch_to_sap(s.sap_prec, vs, gv, st);
+    }
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
     mark(tm, PH_SAP, st);
-    // chi_k = D phi_k in FP64
-    run_dirac(B, P_F64, s.nr_d, B.phi[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
+    // chi_k = D phi_k in FP64 arithmetic
+    run_dirac(B, P_F64, s.nr_d, B.dir[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
     mark(tm, PH_DIRAC, st);
-    // classical Gram-Schmidt: all inner products, then the update of chi_k and r; a system
-    // whose first pass cancelled takes a second pass (RED_GS2, k_gs_update2)
+    // classical Gram-Schmidt: all inner products, then the update of chi_k and r (and the
+    // next preconditioner input); a system whose first pass cancelled takes a second pass
+    // (RED_GS2, k_gs_update2)
+    VecLaunch vu = va;
+    vu.sp = B.sap_rho.data();
+    vu.sp_sc = B.sap_rho.scale();
+    vu.fuse_sap = k + 1 < s.nkv;
     launch_gs_dots(va, gv, st);
     launch_reduce(RED_GS, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    launch_gs_update(va, gv, st);
+    launch_gs_update(s.sap_prec, vu, gv, st);
     launch_reduce(RED_GS2, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    launch_gs_update2(va, gv, st);
+    launch_gs_update2(s.sap_prec, vu, gv, st);
     launch_reduce(RED_RNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
     mark(tm, PH_BLAS, st);
   }
   // x += sum alpha phi; r = b - D x in FP64
   launch_backsub(va, B.nsys, st);
-  launch_x_update(va, gv, st);
+  launch_x_update_dir(va, gv, st);
   mark(tm, PH_BLAS, st);
   run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
   mark(tm, PH_DIRAC, st);
@@ -750,7 +777,11 @@ static std::string graph_key(const Batch& B, const SolveSetup& s) {
   for (int i = 0; i < s.nkv; ++i) {
     add(B.chi[i].data());
     add(B.phi[i].data());
+    add(B.dir[i].data());
+    add(B.dir[i].scale());
   }
+  add(B.d_dir.p);
+  add(B.d_dir_sc.p);
   for (const Field* f : {&B.sap_rho, &B.sap_z, &B.sap_psi}) {
     add(f->data());
     add(f->scale());
@@ -912,7 +943,7 @@ static VecLaunch arn_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
 }
 
 static void prepare_fgmres(Batch& B, const SolveSetup& s) {
-  prepare_solver(B, s);
+  prepare_solver(B, s, false);
   B.arn_vlast.ensure(P_F64, B.sites_rhs);
   std::vector<double2*> pv(NKV_MAX + 1, nullptr);
   for (int k = 0; k < s.nkv; ++k) pv[k] = B.chi[k].d.as<double2>();
@@ -1427,6 +1458,7 @@ int wc_apply_D_noalloc(wc_ctx* c, void* out, const void* in, int nrhs, int prec,
     a.nitems = (int)nitems;
     a.in = fin;
     a.in_sc = fin_sc;
+    a.in_prec = prec;
     a.out = fout;
     a.out_sc = fout_sc;
     a.y = nullptr;

@@ -30,21 +30,22 @@ __global__ __launch_bounds__(WG) void k_to_sap(VecLaunch a) {
   }
 }
 
+// the next preconditioner input eta = r / |r_k| at one site, written by the residual
+// update (|r_k|^2 is still the system's rnorm2 there: the reduction after the update
+// replaces it); any positive scale would do, the preconditioner's storage only needs r
+// brought to a modest range
 template <int P>
-__global__ __launch_bounds__(WG) void k_from_sap(VecLaunch a) {
-  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
-    VecSite v = vec_site(a, it0);
-    if (a.skip[v.sys] || !v.valid) continue;
-    const double sc = sqrt(a.sys[v.sys].rnorm2);
-    auto p = SpinorIO<P>::load(
-        FieldRef{(char*)a.sp + v.off * spinor_site_bytes(P), a.sp_sc ? a.sp_sc + v.off : nullptr, v.V}, v.s);
-    Spinor<double> o;
+WC_D void store_sap_input(const VecLaunch& a, const VecSite& v, const Spinor<double>& r) {
+  typedef typename Real<P>::T R;
+  const double n2 = a.sys[v.sys].rnorm2;
+  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
+  Spinor<R> o;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) o.c[i][c] = {sc * double(p.c[i][c].re), sc * double(p.c[i][c].im)};
-    st64(a.phi[a.k], v, o);
-  }
+    for (int c = 0; c < 3; ++c) o.c[i][c] = {R(r.c[i][c].re * inv), R(r.c[i][c].im * inv)};
+  SpinorIO<P>::store(FieldRef{(char*)a.sp + v.off * spinor_site_bytes(P), a.sp_sc ? a.sp_sc + v.off : nullptr, v.V},
+                     v.s, o);
 }
 
 // ------------------------------------------------------------------ Gram-Schmidt
@@ -117,11 +118,13 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   }
 }
 
-// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2.
+// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2; with
+// fuse_sap also the next preconditioner input r / |r_k| (storage P).
 // A system flagged by the reduction for a second pass (S.reorth) instead stores
 // chi_k' = chi_k - sum_l a_lk chi_l and the partial sums of the second pass,
 //   a2_l = <chi_l, chi_k'> (l < k), |chi_k'|^2 and <chi_k', r>,
 // as [2k a2][|chi_k'|^2][2 <chi_k', r>]; r is left for k_gs_update2.
+template <int P>
 __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (2 * NKV_MAX + 4)];
   const int k = a.k;
@@ -203,6 +206,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
         }
       st64(a.chi[k], v, ck);
       st64(a.r, v, r);
+      if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
     put_partial<1>(a, v, vals, lds);
     __syncthreads();
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
 
 // Second Gram-Schmidt pass of the flagged systems: chi_k <- (chi_k' - sum_l a2_l chi_l) / b_k;
 // r <- r - c_k chi_k; partial |r|^2.  Other systems were finished by k_gs_update.
+template <int P>
 __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
   __shared__ double lds[(WG / 64)];
   const int k = a.k;
@@ -243,6 +248,7 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
         }
       st64(a.chi[k], v, ck);
       st64(a.r, v, r);
+      if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
     put_partial<1>(a, v, vals, lds);
     __syncthreads();
@@ -263,6 +269,31 @@ __global__ __launch_bounds__(WG) void k_x_update(VecLaunch a) {
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) cmac(x.c[i][c], al, p.c[i][c]);
+    }
+    st64(a.x, v, x);
+  }
+}
+
+// x += sum_{l < k_done} alpha_l phi_l with phi_l the preconditioner's output in its storage
+template <int P>
+__global__ __launch_bounds__(WG) void k_x_update_dir(VecLaunch a) {
+  for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
+    VecSite v = vec_site(a, it0);
+    const SysState& S = a.sys[v.sys];
+    if (S.converged || !v.valid) continue;
+    Spinor<double> x = ld64(a.x, v);
+    for (int l = 0; l < S.k_done; ++l) {
+      const cplx<double> al = {S.alpha[l].x, S.alpha[l].y};
+      const FieldRef f{(char*)a.dir[l] + v.off * spinor_site_bytes(P), a.dir_sc[l] ? a.dir_sc[l] + v.off : nullptr,
+                       v.V};
+      // the direction as FP64 D used it: stored value times site scale, formed in double
+      const auto p = SpinorIO<P>::load_raw(f, v.s);
+      const double sc = double(SpinorIO<P>::scale(f, v.s));
+      const cplx<double> as = {al.re * sc, al.im * sc};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cmac(x.c[i][c], as, cplx<double>{double(p.c[i][c].re), double(p.c[i][c].im)});
     }
     st64(a.x, v, x);
   }
@@ -478,18 +509,32 @@ void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
     default: launch_vec(k_to_sap<P_BF16>, a, grid, st); break;
   }
 }
-void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
-  switch (prec) {
-    case P_F64: launch_vec(k_from_sap<P_F64>, a, grid, st); break;
-    case P_F32: launch_vec(k_from_sap<P_F32>, a, grid, st); break;
-    case P_F16: launch_vec(k_from_sap<P_F16>, a, grid, st); break;
-    default: launch_vec(k_from_sap<P_BF16>, a, grid, st); break;
+void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_dots, a, grid, st); }
+void launch_gs_update(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  switch (sap_prec) {
+    case P_F64: launch_vec(k_gs_update<P_F64>, a, grid, st); break;
+    case P_F32: launch_vec(k_gs_update<P_F32>, a, grid, st); break;
+    case P_F16: launch_vec(k_gs_update<P_F16>, a, grid, st); break;
+    default: launch_vec(k_gs_update<P_BF16>, a, grid, st); break;
   }
 }
-void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_dots, a, grid, st); }
-void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update, a, grid, st); }
-void launch_gs_update2(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_update2, a, grid, st); }
+void launch_gs_update2(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  switch (sap_prec) {
+    case P_F64: launch_vec(k_gs_update2<P_F64>, a, grid, st); break;
+    case P_F32: launch_vec(k_gs_update2<P_F32>, a, grid, st); break;
+    case P_F16: launch_vec(k_gs_update2<P_F16>, a, grid, st); break;
+    default: launch_vec(k_gs_update2<P_BF16>, a, grid, st); break;
+  }
+}
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_x_update, a, grid, st); }
+void launch_x_update_dir(const VecLaunch& a, int grid, hipStream_t st) {
+  switch (a.dir_prec) {
+    case P_F64: launch_vec(k_x_update_dir<P_F64>, a, grid, st); break;
+    case P_F32: launch_vec(k_x_update_dir<P_F32>, a, grid, st); break;
+    case P_F16: launch_vec(k_x_update_dir<P_F16>, a, grid, st); break;
+    default: launch_vec(k_x_update_dir<P_BF16>, a, grid, st); break;
+  }
+}
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_norm2, dim3(grid), dim3(WG), 0, st, a, v);
 }

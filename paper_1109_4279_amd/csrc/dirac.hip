@@ -22,10 +22,21 @@ template <class R> WC_D void g5(Spinor<R>& p) {
   }
 }
 
+template <class R, class T> WC_D Spinor<R> to_real(const Spinor<T>& p) {
+  Spinor<R> o;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.c[i][c] = {R(p.c[i][c].re), R(p.c[i][c].im)};
+  return o;
+}
+
 // STAGE: every work item is one 256-site tile (Schwarz blocks of 256 sites); the tile's
 // input spinors are decoded once into LDS and the in-tile neighbours are read from there,
 // so each spinor leaves HBM/L2 once per tile instead of once per neighbour.
-template <int P, int NR, bool STAGE>
+// PIN: storage precision of the input (FP64 arithmetic may read a reduced-precision input,
+// converted exactly to double; every other launch reads its own precision).
+template <int P, int NR, bool STAGE, int PIN = P>
 __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
   typedef typename Real<P>::T R;
   __shared__ double red[(WG / 64) * NR];
@@ -51,12 +62,12 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
     local_coords(g, s - tile * g.bvol, lc);
 
     FieldRef fin[NR], fout[NR], fy[NR];
-    const int sb = spinor_site_bytes(P);
+    const int sb = spinor_site_bytes(P), sbin = spinor_site_bytes(PIN);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int rr = w.rhs0 + (r < w.nr ? r : 0);
       const long long off = L.foff + (long long)rr * g.V;
-      fin[r] = {(char*)a.in + off * sb, a.in_sc ? (float*)a.in_sc + off : nullptr, g.V};
+      fin[r] = {(char*)a.in + off * sbin, a.in_sc ? (float*)a.in_sc + off : nullptr, g.V};
       fout[r] = {(char*)a.out + off * sb, a.out_sc ? a.out_sc + off : nullptr, g.V};
       fy[r] = {a.y ? (char*)a.y + off * sb : nullptr, a.y_sc ? (float*)a.y_sc + off : nullptr, g.V};
     }
@@ -67,10 +78,10 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
     if (STAGE) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        Spinor<R> p = SpinorIO<P>::load_raw(fin[r], s);
+        Spinor<R> p = to_real<R>(SpinorIO<PIN>::load_raw(fin[r], s));
 #pragma unroll
         for (int k = 0; k < 12; ++k) st_sp[(r * 12 + k) * WG + threadIdx.x] = p.c[k / 3][k % 3];
-        st_sc[r * WG + threadIdx.x] = SpinorIO<P>::scale(fin[r], s);
+        st_sc[r * WG + threadIdx.x] = SpinorIO<PIN>::scale(fin[r], s);
       }
       __syncthreads();
     }
@@ -83,8 +94,8 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
         for (int k = 0; k < 12; ++k) p.c[k / 3][k % 3] = st_sp[(r * 12 + k) * WG + ln];
         sc = st_sc[r * WG + ln];
       } else {
-        p = SpinorIO<P>::load_raw(fin[r], n);
-        sc = SpinorIO<P>::scale(fin[r], n);
+        p = to_real<R>(SpinorIO<PIN>::load_raw(fin[r], n));
+        sc = SpinorIO<PIN>::scale(fin[r], n);
       }
       return p;
     };
@@ -200,31 +211,39 @@ size_t dirac_stage_lds_bytes(int prec, int nr) {
   return (2 * real * 12 + real) * (size_t)std::min(std::max(nr, 1), 4) * WG;
 }
 
-template <int P, bool S>
+template <int P, bool S, int PIN>
 static void launch_ps(const DiracLaunch& a, int nr, int grid, hipStream_t st) {
   auto lds = [&](int n) { return S ? dirac_stage_lds_bytes(P, n) : size_t(0); };
   switch (nr) {
-    case 1: hipLaunchKernelGGL((k_dirac<P, 1, S>), dim3(grid), dim3(WG), lds(1), st, a); break;
-    case 2: hipLaunchKernelGGL((k_dirac<P, 2, S>), dim3(grid), dim3(WG), lds(2), st, a); break;
-    case 3: hipLaunchKernelGGL((k_dirac<P, 3, S>), dim3(grid), dim3(WG), lds(3), st, a); break;
-    default: hipLaunchKernelGGL((k_dirac<P, 4, S>), dim3(grid), dim3(WG), lds(4), st, a); break;
+    case 1: hipLaunchKernelGGL((k_dirac<P, 1, S, PIN>), dim3(grid), dim3(WG), lds(1), st, a); break;
+    case 2: hipLaunchKernelGGL((k_dirac<P, 2, S, PIN>), dim3(grid), dim3(WG), lds(2), st, a); break;
+    case 3: hipLaunchKernelGGL((k_dirac<P, 3, S, PIN>), dim3(grid), dim3(WG), lds(3), st, a); break;
+    default: hipLaunchKernelGGL((k_dirac<P, 4, S, PIN>), dim3(grid), dim3(WG), lds(4), st, a); break;
   }
 }
 
-template <int P>
+template <int P, int PIN>
 static void launch_p(const DiracLaunch& a, int nr, int grid, hipStream_t st) {
   if (a.stage)
-    launch_ps<P, true>(a, nr, grid, st);
+    launch_ps<P, true, PIN>(a, nr, grid, st);
   else
-    launch_ps<P, false>(a, nr, grid, st);
+    launch_ps<P, false, PIN>(a, nr, grid, st);
 }
 
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st) {
+  if (prec == P_F64) {
+    switch (a.in_prec) {
+      case P_F64: launch_p<P_F64, P_F64>(a, nr, grid, st); break;
+      case P_F32: launch_p<P_F64, P_F32>(a, nr, grid, st); break;
+      case P_F16: launch_p<P_F64, P_F16>(a, nr, grid, st); break;
+      default: launch_p<P_F64, P_BF16>(a, nr, grid, st); break;
+    }
+    return;
+  }
   switch (prec) {
-    case P_F64: launch_p<P_F64>(a, nr, grid, st); break;
-    case P_F32: launch_p<P_F32>(a, nr, grid, st); break;
-    case P_F16: launch_p<P_F16>(a, nr, grid, st); break;
-    default: launch_p<P_BF16>(a, nr, grid, st); break;
+    case P_F32: launch_p<P_F32, P_F32>(a, nr, grid, st); break;
+    case P_F16: launch_p<P_F16, P_F16>(a, nr, grid, st); break;
+    default: launch_p<P_BF16, P_BF16>(a, nr, grid, st); break;
   }
 }
 

@@ -25,6 +25,7 @@ struct DiracLaunch {
   int dagger;          // apply gamma5 D gamma5
   int block;           // Dirichlet-block operator instead of the full one
   int stage;           // every lattice has 256-site tiles: stage each tile's input in LDS
+  int in_prec;         // storage precision of `in` (may differ from the launch's only for FP64)
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
 size_t dirac_stage_lds_bytes(int prec, int nr);  // dynamic LDS of a staged D_w launch
@@ -156,17 +157,26 @@ struct VecLaunch {
   // SAP-precision field for conversions
   void* sp; float* sp_sc;
   ArnState* arn;           // FGMRES-DR state per system (null for FGCR)
+  // FGCR: the search directions phi_l as the preconditioner wrote them (storage dir_prec,
+  // device arrays of NKV_MAX data / scale pointers), and whether the residual update also
+  // writes the next preconditioner input r / |r_k| into sp (all but a cycle's last step)
+  void* const* dir;
+  float* const* dir_sc;
+  int dir_prec;
+  int fuse_sap;
 };
-// phi_k = |r| * psi(P)      (psi from the SAP) ; eta(P) = r / |r|
+// eta(P) = r / |r|, the preconditioner's input at the start of a restart cycle (later
+// steps get theirs from the residual update); the FGCR direction phi_k is the
+// preconditioner's output as stored (GCR is invariant to the scale of a direction)
 void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
-void launch_from_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
 void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, <chi_l, r>, |chi_k|^2, <chi_k, r>
 // chi_k = (chi_k - sum a_lk chi_l)/b_k; r -= c_k chi_k; |r|^2.  A system whose first pass
 // cancelled (reorth) instead keeps chi_k - sum a_lk chi_l and its second-pass dots, and
 // launch_gs_update2 finishes it after the RED_GS2 reduction.
-void launch_gs_update(const VecLaunch& a, int grid, hipStream_t st);
-void launch_gs_update2(const VecLaunch& a, int grid, hipStream_t st);
-void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l
+void launch_gs_update(int sap_prec, const VecLaunch& a, int grid, hipStream_t st);
+void launch_gs_update2(int sap_prec, const VecLaunch& a, int grid, hipStream_t st);
+void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l (FP64 phi)
+void launch_x_update_dir(const VecLaunch& a, int grid, hipStream_t st); // x += sum alpha_l dir_l
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials
 void launch_copy_f64(const VecLaunch& a, double2* dst, const double2* src, int grid, hipStream_t st);
 void launch_zero_if_b0(const VecLaunch& a, double2* x, int grid, hipStream_t st);  // x = 0 where |b| = 0
