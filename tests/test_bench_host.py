@@ -14,20 +14,27 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_flop_counts():
-    # plain MR: n_mr (D_Lambda + MR vector work) + the initial residual copy
-    assert bench.half_sweep_flops_per_site(4, False) == 4 * (1824 + 336) + 24
-    # even/odd: the Schur complement touches every block site once per step, vector work on
-    # the even half, one more block sweep for the source and the odd half
-    assert bench.half_sweep_flops_per_site(4, True) == 4 * (1824 + 168) + 1824 + 24
-    assert bench.sap_flops_per_site(5, 4, True) == 5 * bench.half_sweep_flops_per_site(4, True) + 4.5 * 336
-    # one iteration, one cycle: preconditioner + scalings, chi = D phi, GS with k = 0, x update, true residual
-    V = 10
-    one = (bench.sap_flops_per_site(5, 4) + 48 + 1824 + 144 + 168 + 96 + 1824 + 72) * V
-    assert bench.solve_flops(V, 1, 1, 16, 5, 4) == pytest.approx(one)
-    # iterations spread over restarts: the second cycle restarts the Gram-Schmidt count
-    two_cycles = bench.solve_flops(V, 4, 2, 2, 5, 4)
-    assert two_cycles == pytest.approx(2 * bench.solve_flops(V, 2, 1, 2, 5, 4))
+def test_flop_and_byte_counts():
+    # D_Lambda on 4^4 blocks: 6 of the 8 hops stay in the block (144 flops each), 5
+    # accumulates of 24, both clover blocks 504
+    assert bench.mean_inblock_hops((4, 4, 4, 4)) == 6.0
+    assert bench.dlambda_flops((4, 4, 4, 4)) == 6 * 144 + 5 * 24 + 504 == 1488
+    # even/odd half-sweep per solved site: 4 Schur steps (operator + half the MR vector work),
+    # one more block sweep for the source and the odd half, 12, the 2 border hops with their
+    # accumulates, and psi += z
+    assert bench.half_sweep_flops((4, 4, 4, 4), 4, True) == 4 * (1488 + 168) + 1488 + 12 + 2 * 168 + 24 == 8484
+    assert bench.half_sweep_flops((4, 4, 4, 4), 4, True, executed=False) == 4 * (1824 + 168) + 1824 + 12 + 336 + 24
+    assert bench.half_sweep_flops((4, 4, 4, 4), 4, False) == 4 * (1488 + 336) + 336 + 24
+    # bytes: 16-bit operator 148 + 152, six 52-byte spinor passes; D_w FP64 1536 per site
+    assert bench.half_sweep_bytes("bf16") == 612
+    assert bench.half_sweep_bytes("bf16", tile=12) == pytest.approx(300 / 12 + 312)
+    assert bench.dw_bytes("f64") == 1536 and bench.dw_bytes("f32", tile=2) == 192 + 288
+    # one FGCR iteration in one cycle: SAP (ncy half-sweeps over half the sites each, counted
+    # per site) + scalings, D, Gram-Schmidt with k = 0, then the x update and true residual
+    one = (5 * bench.half_sweep_flops((4, 4, 4, 4), 4, True) + 48 + 1824 + 144 + 168 + 96 + 1824 + 72) * 10
+    assert bench.solve_flops(10, 1, 1, 16, 5, 4, (4, 4, 4, 4), True) == pytest.approx(one)
+    two = bench.solve_flops(10, 4, 2, 2, 5, 4, (4, 4, 4, 4), True)
+    assert two == pytest.approx(2 * bench.solve_flops(10, 2, 1, 2, 5, 4, (4, 4, 4, 4), True))
 
 
 def _pmc_csv(path, counter, rows):
@@ -69,11 +76,12 @@ def test_traffic_record_is_dropped_when_the_sources_change(tmp_path, monkeypatch
     _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(copy, float(1 << 20))] + [(k, 4.0)] * 20)
     _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(copy, float(1 << 20))] + [(k, 1.0)] * 20)
     bench.summarise_pmc(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
-                        str(tmp_path / "profiles" / "traffic_16c32.json"))
-    assert bench.measured_traffic("k_x") == pytest.approx(5.0 * 1024)
-    assert bench.measured_traffic("k_missing") is None
+                        str(tmp_path / "profiles" / "traffic_24c48.json"))
+    assert bench.measured_traffic("k_x", "traffic_24c48.json") == pytest.approx(5.0 * 1024)
+    assert bench.measured_traffic("k_missing", "traffic_24c48.json") is None
+    assert bench.measured_traffic("k_x", "missing.json") is None
     (src / "k.hip").write_text("kernel source, changed\n")
-    assert bench.measured_traffic("k_x") is None
+    assert bench.measured_traffic("k_x", "traffic_24c48.json") is None
 
 
 def test_more_than_one_gpu_is_refused():
@@ -83,48 +91,29 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_profile_report(tmp_path):
-    """The profile summary: kernel statistics, last-20-dispatch averages beside the bench
-    figures, the traffic table per site, and every command that made it."""
-    stats = tmp_path / "stats"
-    stats.mkdir()
-    k = "void wc::k_sap_eo<1, 1, true>(wc::SapLaunch)"
-    with open(stats / "run_kernel_stats.csv", "w", newline="") as f:
-        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "AverageNs", "Percentage"])
+def test_profile_summary(tmp_path):
+    """The committed profile summary: kernels by total time, the last 20 dispatches' mean
+    beside the overall mean, the traffic per launch when a record is given, the command."""
+    k = "void wc::k_sap_eo<3, 1, false>(wc::SapLaunch)"
+    g = "wc::k_gs_dots(wc::VecLaunch)"
+    with open(tmp_path / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
         w.writeheader()
-        w.writerow({"Name": k, "Calls": 25, "AverageNs": 50000.0, "Percentage": 70.0})
-    with open(stats / "run_kernel_trace.csv", "w", newline="") as f:
+        w.writerow({"Name": g, "Calls": 2, "TotalDurationNs": 2000.0, "AverageNs": 1000.0, "Percentage": 10.0})
+        w.writerow({"Name": k, "Calls": 25, "TotalDurationNs": 25 * 50000.0, "AverageNs": 50000.0,
+                    "Percentage": 90.0})
+    with open(tmp_path / "run_kernel_trace.csv", "w", newline="") as f:
         w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
         w.writeheader()
-        # two solves (|b|^2, three half-sweeps, 1 us apart), then 5 warm-up dispatches of
-        # 90 us and 20 of 47 us of the timing loop
-        for t0 in (0, 50 * 10 ** 6):
-            w.writerow({"Kernel_Name": "wc::k_norm2(wc::VecLaunch)", "Start_Timestamp": t0,
-                        "End_Timestamp": t0 + 10000})
-            for j in range(3):
-                w.writerow({"Kernel_Name": k, "Start_Timestamp": t0 + 11000 + j * 48000,
-                            "End_Timestamp": t0 + 11000 + j * 48000 + 47000})
         for i in range(25):
-            t0 = 100 * 10 ** 6 + i * 10 ** 6
-            w.writerow({"Kernel_Name": k, "Start_Timestamp": t0, "End_Timestamp": t0 + (90000 if i < 5 else 47000)})
-    rec = {"metric": "m", "roofline": {"launch_ms": 0.0475, "plain_mr_half_sweep_ms": 0.036},
-           "dirac": {p: {"ms": 0.02} for p in ("f64", "f32", "f16", "bf16")}}
-    (tmp_path / "prof.log").write_text("noise\n" + json.dumps(rec) + "\n")
-    (tmp_path / "bench.json").write_text(json.dumps(rec) + "\n")
-    traffic = {"fetch_scale": 2.0, "write_scale": 1.0,
-               "kernels": {"k_sap_eo<1, 1, true>": {"fetch_bytes": 131072 * 638.0, "write_bytes": 131072 * 144.0}}}
-    (tmp_path / "t.json").write_text(json.dumps(traffic))
-    out = tmp_path / "r.md"
-    bench.profile_report(str(stats), str(tmp_path / "prof.log"), str(tmp_path / "bench.json"),
-                         "pf/f_counter_collection.csv", "pw/w_counter_collection.csv", str(tmp_path / "t.json"),
-                         str(out))
-    md = out.read_text()
-    assert f"| `{k}` | 25 | 50.00 | 70.0 |" in md
-    assert "(dominant kernel, 4 steps) | 47.00 | 47.50 |" in md
-    assert "| `k_sap_eo<1, 1, true>` (one colour) | 638 | 144 |" in md
-    assert "rocprofv3 --pmc FETCH_SIZE --output-format csv -d pf -o f -- python -u bench.py --profile" in md
-    assert "rocprofv3 --pmc WRITE_SIZE --output-format csv -d pw -o w -- " in md
-    assert f"python bench.py --profile-report {stats} " in md
-    # the second solve: 4 kernels, 0.151 ms of kernels in a 0.154 ms span
-    assert "4 kernels,\n0.15 ms of kernels in a 0.15 ms span" in md
-    assert "| `k_sap_eo<1, 1, true>` | 0.141 |" in md
+            t0 = i * 10 ** 6
+            w.writerow({"Kernel_Name": k, "Start_Timestamp": t0, "End_Timestamp": t0 + (90000 if i < 5 else 40000)})
+        for i in range(2):
+            w.writerow({"Kernel_Name": g, "Start_Timestamp": 10 ** 9 + i, "End_Timestamp": 10 ** 9 + i + 1000})
+    (tmp_path / "t.json").write_text(json.dumps({"kernels": {"k_sap_eo<3, 1, false>": {"bytes_per_launch": 2.5e9}}}))
+    lines = bench.profile_summary(str(tmp_path), str(tmp_path / "o.md"), "rocprofv3 ... -- python3 bench.py --profile",
+                                  str(tmp_path / "t.json"))
+    md = (tmp_path / "o.md").read_text()
+    assert md.startswith("Command: `rocprofv3 ... -- python3 bench.py --profile`")
+    assert lines[4] == "| `k_sap_eo<3, 1, false>` | 25 | 50.00 | 40.00 | 1.250 | 90.0 | 2500.0 |"
+    assert lines[5] == "| `k_gs_dots` | 2 | 1.00 | 1.00 | 0.002 | 10.0 |  |"
