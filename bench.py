@@ -352,6 +352,7 @@ def extra_workloads(wc, torch, dev, storage, lat_c4, pts):
     c2["link_derivative_ms"] = ms / 10
     out["workload_16c32"] = c2
     out["near_critical_16c32"] = near_critical(wc, torch, lat.block, dev)
+    out["near_critical_quenched_16c32"] = near_critical_quenched(wc, torch, dev, lat.block)
     del lat, b, phi
     # the uneven batch, one batched solve (block shapes chosen by the block autotuner)
     lats, bs = [], []
@@ -417,6 +418,87 @@ def near_critical(wc, torch, block, dev):
     run("fgmres_32", lambda: lat.solve_fgmres_dr(b, k=0, check=False, nkv=32, **kw))
     run("fgmres_dr_32_10", lambda: lat.solve_fgmres_dr(b, k=10, check=False, nkv=32, **kw))
     rec["speedup_dr_vs_fgcr_32"] = rec["fgcr_32"]["ms"] / rec["fgmres_dr_32_10"]["ms"]
+    return rec
+
+
+QUENCHED_BETA = 6.0
+QUENCHED_CSW = 1.769  # non-perturbative c_sw at beta = 6.0 (ALPHA, Nucl. Phys. B 491 (1997) 323)
+
+
+def critical_mass(wc, torch, U, dims, csw, block, m0_ref, dev, nev=12, seed=None):
+    """Estimate of the critical bare mass of one gauge field by shift-invert Arnoldi: nev
+    steps of Arnoldi (modified Gram-Schmidt, FP64 on the device) on D(m0_ref)^-1, each
+    application a solve of the library's FGMRES-DR (FP32 even/odd SAP, 1e-10); the Ritz
+    values theta of the small Hessenberg matrix give eigenvalue estimates 1/theta of
+    D(m0_ref) closest to zero (conjugate pairs resolved, as D is gamma_5-hermitian).  The
+    spectrum moves rigidly with m0, so the estimate closest to zero, lambda, reaches the
+    imaginary axis at m0_c = m0_ref - Re lambda (the critical mass when it is real).
+    Returns (m0_c, estimates sorted by modulus as [re, im] pairs)."""
+    import numpy as np
+
+    import synth
+    lat = wc.Lattice(U, block=block, m0=m0_ref, csw=csw)
+    v = torch.from_numpy(synth.gaussian_spinor(dims, seed=synth.RHS_SEED if seed is None else seed)).to(dev)
+    V = [v / torch.linalg.vector_norm(v)]
+    H = np.zeros((nev + 1, nev), dtype=np.complex128)
+    for j in range(nev):
+        w, _st = lat.solve_fgmres_dr(V[j], k=10, nkv=32, tol=1e-10, sap_prec="f32", eo=1, ncy=NCY, nmr=NMR,
+                                     maxit=4000)
+        for i in range(j + 1):
+            h = torch.vdot(V[i].flatten(), w.flatten())
+            H[i, j] = complex(h)
+            w = w - h * V[i]
+        H[j + 1, j] = float(torch.linalg.vector_norm(w))
+        V.append(w / H[j + 1, j])
+    del lat, V
+    lam = 1.0 / np.linalg.eigvals(H[:nev, :nev])
+    lam = lam[np.argsort(np.abs(lam))]
+    return m0_ref - lam[0].real, [[z.real, z.imag] for z in lam]
+
+
+def near_critical_quenched(wc, torch, dev, block):
+    """The near-critical stress workload on a self-generated ensemble: a quenched 16^3 x 32
+    field at beta = 6.0 (Wilson action; cold start, 20 x (1 heatbath + 4 overrelaxation)
+    sweeps on the GPU), c_sw = 1.769, its critical mass estimated by shift-invert Arnoldi (two
+    stages, the second 0.02 above the first estimate), then FGCR(16), FGCR(32) and
+    FGMRES-DR(32, 10) on a Gaussian source at 0.02 and 0.005 above it (FP32 even/odd SAP,
+    FP64 outer, tol 1e-10, maxit 3000): the regime of Fig. 1, where restarted GCR slows down
+    and deflated restarts keep the low modes."""
+    import synth
+    from synth import quenched
+    t0 = time.perf_counter()
+    hist = []
+    U = quenched.ensemble(C2_DIMS, beta=QUENCHED_BETA, ntherm=20, nor=4, device=dev, history=hist)
+    torch.cuda.synchronize()
+    rec = {"ensemble": {"dims": list(C2_DIMS), "beta": QUENCHED_BETA, "csw": QUENCHED_CSW,
+                        "sweeps": "20 x (1 heatbath + 4 overrelaxation), cold start",
+                        "generation_s": time.perf_counter() - t0, "plaquette_history": hist}}
+    c1, l1 = critical_mass(wc, torch, U, C2_DIMS, QUENCHED_CSW, block, -0.25, dev)
+    c2, l2 = critical_mass(wc, torch, U, C2_DIMS, QUENCHED_CSW, block, c1 + 0.02, dev)
+    rec["critical_mass"] = {"method": "shift-invert Arnoldi, 12 solves per stage",
+                            "stage1": {"m0_ref": -0.25, "m0_c": c1, "lowest_eigenvalues": l1[:6]},
+                            "stage2": {"m0_ref": c1 + 0.02, "m0_c": c2, "lowest_eigenvalues": l2[:6]},
+                            "estimate": c2}
+    b = torch.from_numpy(synth.gaussian_spinor(C2_DIMS)).to(dev)
+    kw = dict(ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f32", eo=1, maxit=3000)
+    for dm in (0.02, 0.005):
+        lat = wc.Lattice(U, block=block, m0=c2 + dm, csw=QUENCHED_CSW)
+        r = {"m0": c2 + dm}
+
+        def run(name, f):
+            f()
+            (_, st), ms = sync_time(torch, f)
+            r[name] = {"ms": ms, "iters": st[0]["iters"], "restarts": st[0]["restarts"],
+                       "true_rel_residual": st[0]["rel_true_res"], "status": st[0]["status"],
+                       "gram_schmidt_second_passes": st[0]["reorth"]}
+
+        run("fgcr_16", lambda: lat.solve(b, check=False, nkv=16, **kw))
+        run("fgcr_32", lambda: lat.solve(b, check=False, nkv=32, **kw))
+        run("fgmres_dr_32_10", lambda: lat.solve_fgmres_dr(b, k=10, check=False, nkv=32, **kw))
+        r["speedup_dr_vs_fgcr_32"] = r["fgcr_32"]["ms"] / r["fgmres_dr_32_10"]["ms"]
+        rec[f"dm_{dm}"] = r
+        del lat
+    del U
     return rec
 
 
@@ -489,9 +571,42 @@ def profile_run(wc, torch, dev):
                       "dirac_12rhs": dw}), flush=True)
 
 
+def profile_summary(stats_dir, out_md, command, traffic_json=None, top=16):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run of `bench.py --profile`:
+    per-kernel calls, mean and total time from the stats CSV, the mean of each kernel's last
+    20 dispatches from the trace (the timing loops bench.py reports), and, with a traffic
+    record, the HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE passes."""
+    import csv
+    stats = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_stats.csv"))))
+    stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    trace = list(csv.DictReader(open(os.path.join(stats_dir, "run_kernel_trace.csv"))))
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    durs = {}
+    for r in trace:
+        durs.setdefault(r["Kernel_Name"], []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    traffic = json.load(open(traffic_json))["kernels"] if traffic_json else {}
+    lines = [f"Command: `{command}`", "", "| kernel | calls | mean us | last 20 mean us | total ms | % | "
+             "HBM MB / launch (last 20) |", "|---|---|---|---|---|---|---|"]
+    for r in stats[:top]:
+        name = r["Name"]
+        last = durs.get(name, [])[-20:]
+        short = name.replace("void ", "").replace("wc::", "").split("(")[0]
+        t = traffic.get(short)
+        mb = f"{t['bytes_per_launch'] / 1e6:.1f}" if t else ""
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{(sum(last) / len(last)) if last else 0.0:.2f} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['Percentage']):.1f} | {mb} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    return lines
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
         summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--profile-summary":
+        # --profile-summary STATS_DIR OUT_MD COMMAND [TRAFFIC_JSON]
+        profile_summary(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else None)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
