@@ -394,11 +394,14 @@ struct Batch {
   const ItemList& items_dirac(int nr) {
     auto it = dirac_items.find(nr);
     if (it != dirac_items.end()) return it->second;
+    // chunk-major: the items of one chunk's rhs tiles are consecutive, so one XCD runs them
+    // at about the same time and its L2 serves the chunk's links and clover blocks to all
+    // of them after one read from memory
     std::vector<WorkItem> v;
     for (size_t i = 0; i < lat.size(); ++i) {
       const int nch = (lat[i]->g.V + WG - 1) / WG;
-      for (int r0 = 0; r0 < nrhs[i]; r0 += nr)
-        for (int c = 0; c < nch; ++c) v.push_back(WorkItem{(int)i, c, r0, std::min(nr, nrhs[i] - r0)});
+      for (int c = 0; c < nch; ++c)
+        for (int r0 = 0; r0 < nrhs[i]; r0 += nr) v.push_back(WorkItem{(int)i, c, r0, std::min(nr, nrhs[i] - r0)});
     }
     ItemList& L = dirac_items[nr];
     L.d.ensure(sizeof(WorkItem) * v.size());
