@@ -285,7 +285,7 @@ struct Batch {
   bool have_lats[4] = {false, false, false, false};
   bool lats_eo[4] = {false, false, false, false};  // descriptors carry the even/odd clover
   std::map<int, ItemList> dirac_items;      // by RHS tile
-  std::map<int, ItemList> sap_items[2];     // by RHS tile
+  std::map<int, ItemList> sap_items[2];     // by RHS tile and block volume
   DevBuf sys_part, sys_nchunks;
   DevBuf partials;
   int pw = 4 * NKV_MAX;  // partial-sum width (at most RWG: sum_partials)
@@ -391,35 +391,51 @@ struct Batch {
     return d_lats[prec].as<LatDesc>();
   }
 
-  const ItemList& items_dirac(int nr) {
-    auto it = dirac_items.find(nr);
+  // D_w items of rhs tile nr over the lattices selected by sel: 0 every lattice, 1 those
+  // with 256-site blocks (whose chunks are blocks, so a launch may stage them), 2 the others
+  const ItemList& items_dirac(int nr, int sel = 0) {
+    const int key = 4 * nr + sel;
+    auto it = dirac_items.find(key);
     if (it != dirac_items.end()) return it->second;
     // chunk-major: the items of one chunk's rhs tiles are consecutive, so one XCD runs them
     // at about the same time and its L2 serves the chunk's links and clover blocks to all
     // of them after one read from memory
     std::vector<WorkItem> v;
     for (size_t i = 0; i < lat.size(); ++i) {
+      if ((sel == 1 && lat[i]->g.bvol != 256) || (sel == 2 && lat[i]->g.bvol == 256)) continue;
       const int nch = (lat[i]->g.V + WG - 1) / WG;
       for (int c = 0; c < nch; ++c)
         for (int r0 = 0; r0 < nrhs[i]; r0 += nr) v.push_back(WorkItem{(int)i, c, r0, std::min(nr, nrhs[i] - r0)});
     }
-    ItemList& L = dirac_items[nr];
+    ItemList& L = dirac_items[key];
     L.d.ensure(sizeof(WorkItem) * v.size());
     HIPCK(hipMemcpy(L.d.p, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
     L.n = (int)v.size();
     return L;
   }
 
-  const ItemList& items_sap(int colour, int nr) {
-    auto it = sap_items[colour].find(nr);
+  // the block volumes of the batch, largest first
+  std::vector<int> bvols() const {
+    std::vector<int> v;
+    for (auto* c : lat)
+      if (std::find(v.begin(), v.end(), c->g.bvol) == v.end()) v.push_back(c->g.bvol);
+    std::sort(v.rbegin(), v.rend());
+    return v;
+  }
+
+  // block-solver items of the lattices with block volume bvol (0: every lattice)
+  const ItemList& items_sap(int colour, int nr, int bvol = 0) {
+    const int key = nr * 65536 + bvol;
+    auto it = sap_items[colour].find(key);
     if (it != sap_items[colour].end()) return it->second;
     std::vector<WorkItem> v;
     for (size_t i = 0; i < lat.size(); ++i) {
+      if (bvol && lat[i]->g.bvol != bvol) continue;
       const int nt = lat[i]->g.ntiles / 2;
       for (int t = 0; t < nt; ++t)
         for (int r0 = 0; r0 < nrhs[i]; r0 += nr) v.push_back(WorkItem{(int)i, t, r0, std::min(nr, nrhs[i] - r0)});
     }
-    ItemList& L = sap_items[colour][nr];
+    ItemList& L = sap_items[colour][key];
     L.d.ensure(sizeof(WorkItem) * v.size());
     HIPCK(hipMemcpy(L.d.p, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
     L.n = (int)v.size();
@@ -439,7 +455,43 @@ static Batch& ctx_batch(wc_ctx* c, int nrhs) {
   return ref;
 }
 
-static void invalidate_batches(wc_ctx* c) { c->batches.clear(); }
+// Batches over several lattices, kept like the single-lattice ones (fields, item lists and
+// captured graphs survive between calls) and keyed by the lattices and their rhs counts.
+// A map on the heap that is never freed: entries go when one of their contexts changes its
+// layout or is destroyed, and whatever a program leaks is not freed after the runtime.
+using MultiKey = std::pair<std::vector<wc_ctx*>, std::vector<int>>;
+static std::map<MultiKey, std::unique_ptr<Batch>>& multi_batches() {
+  static auto* m = new std::map<MultiKey, std::unique_ptr<Batch>>();
+  return *m;
+}
+
+static Batch& multi_batch(const std::vector<wc_ctx*>& ctxs, const std::vector<int>& nrhs) {
+  auto& m = multi_batches();
+  MultiKey key{ctxs, nrhs};
+  auto it = m.find(key);
+  if (it != m.end()) return *it->second;
+  auto b = std::make_unique<Batch>();
+  b->init(ctxs, nrhs);
+  Batch& ref = *b;
+  m[key] = std::move(b);
+  return ref;
+}
+
+static void drop_multi_batches(wc_ctx* c) {
+  auto& m = multi_batches();
+  for (auto it = m.begin(); it != m.end();) {
+    const auto& cs = it->first.first;
+    if (std::find(cs.begin(), cs.end(), c) != cs.end())
+      it = m.erase(it);
+    else
+      ++it;
+  }
+}
+
+static void invalidate_batches(wc_ctx* c) {
+  c->batches.clear();
+  drop_multi_batches(c);
+}
 
 static int default_nr(int nrhs, int prec, bool sap, int eo) {
   if (nrhs <= 1) return 1;
@@ -467,20 +519,23 @@ static int pick_nr(wc_ctx* c, int nrhs, int prec, bool sap, int requested, int e
 // pays for FP64 (whose spinors overflow L2 between the nine reads of each) and costs for
 // FP32 / 16-bit (measured on MI355X); the WC_OPT_DIRAC_STAGE option of the batch's first
 // context forces it off/on where allowed.
-static int dirac_stage_mode(const Batch& B, int prec) {
-  if (B.uniform_bvol != 256) return 0;
+// Staging of a D_w launch: 0 none, 1 every item (all blocks have 256 sites), 2 split into
+// a staged launch over the lattices with 256-site blocks and an unstaged one over the rest
+static int dirac_stage_mode(const Batch& B, int prec, int nr) {
   const int forced = B.lat[0]->opt_dirac_stage;
-  return forced >= 0 ? forced : (prec == P_F64 ? 1 : 0);
+  const bool want = forced >= 0 ? forced != 0 : prec == P_F64;
+  if (!want || dirac_stage_lds_bytes(prec, nr) > LDS_MAX_BYTES) return 0;
+  if (B.uniform_bvol == 256) return 1;
+  for (auto* c : B.lat)
+    if (c->g.bvol == 256) return 2;
+  return 0;
 }
 
 static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, const Field* y, double* partials,
                       const int* skip, int dagger, int block, hipStream_t st) {
   const LatDesc* L = B.lats(prec, st);
-  const ItemList& it = B.items_dirac(nr);
   DiracLaunch a;
   a.lats = L;
-  a.items = it.d.as<WorkItem>();
-  a.nitems = it.n;
   a.in = in.data();
   a.in_sc = in.scale();
   a.in_prec = in.prec;
@@ -493,9 +548,17 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   a.skip = skip;
   a.dagger = dagger;
   a.block = block;
-  // a tile of nr rhs that does not fit a work-group's LDS runs unstaged
-  a.stage = dirac_stage_mode(B, prec) && dirac_stage_lds_bytes(prec, nr) <= LDS_MAX_BYTES;
-  launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
+  // (a tile of nr rhs that does not fit a work-group's LDS runs unstaged)
+  const int mode = dirac_stage_mode(B, prec, nr);
+  for (int sel : (mode == 2 ? std::array<int, 2>{1, 2} : std::array<int, 2>{0, -1})) {
+    if (sel < 0) break;
+    const ItemList& it = B.items_dirac(nr, sel);
+    if (it.n == 0) continue;
+    a.items = it.d.as<WorkItem>();
+    a.nitems = it.n;
+    a.stage = (mode == 1 || sel == 1) ? 1 : 0;
+    launch_dirac(prec, nr, a, persistent_grid(it.n, 8), st);
+  }
 }
 
 // Register caching of the block operator pays when the launch has about one work-group
@@ -513,45 +576,51 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
                               const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st,
                               int odd_rho = 0) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
-  // the even/odd solver's border update runs from LDS entries when they fit a work-group's
-  // LDS next to the exchange rows (else per site)
-  int bentries = 0;
-  for (auto* c : B.lat) bentries = std::max(bentries, border_entry_count(c->g.B));
-  if (eo && sap_eo_lds_bytes(prec, nr, B.max_bvol, bentries) > LDS_MAX_BYTES) bentries = 0;
   require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol, 0) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
   const LatDesc* L = B.lats(prec, st, eo != 0);
-  const ItemList& it = B.items_sap(colour, nr);
-  SapLaunch a;
-  a.lats = L;
-  a.items = it.d.as<WorkItem>();
-  a.nitems = it.n;
-  a.colour = colour;
-  a.nmr = nmr;
-  a.rho = rho.data();
-  a.rho_sc = rho.scale();
-  a.z = z.data();
-  a.z_sc = z.scale();
-  a.psi = psi.data();
-  a.psi_sc = psi.scale();
-  a.skip = skip;
-  a.first = first;
-  a.border = border;
-  a.write_rho = wrho;
-  a.write_z = wz;
-  a.cache = sap_cache_mode(B, it.n);
-  a.uniform_bvol = B.uniform_bvol;
-  a.odd_rho = odd_rho;
-  // (with the operator cached the launch has one work-group per CU, and the entries'
-  // extra barrier costs more than the divergent per-site update: measured at 16^3 x 32)
-  a.border_entries = (eo && !a.cache) ? bentries : 0;
-  a.eo_rows = 2 * ((B.max_bvol + 1) / 2);
-  if (eo)
-    launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), B.max_bvol, st);
-  else if (is16(prec) && nr == 2 && B.uniform_bvol == 256)
-    launch_sap_mr_lds(prec, nr, a, persistent_grid(it.n, 1), st);
-  else
-    launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), B.sap_threads(), st);
+  // one launch per block volume of the batch, each with work-groups sized for its own
+  // blocks (one launch sized for the largest would leave the lanes of smaller blocks idle)
+  for (int bv : B.bvols()) {
+    // the even/odd solver's border update runs from LDS entries when they fit a
+    // work-group's LDS next to the exchange rows (else per site)
+    int bentries = 0;
+    for (auto* c : B.lat)
+      if (c->g.bvol == bv) bentries = std::max(bentries, border_entry_count(c->g.B));
+    if (eo && sap_eo_lds_bytes(prec, nr, bv, bentries) > LDS_MAX_BYTES) bentries = 0;
+    const ItemList& it = B.items_sap(colour, nr, bv);
+    if (it.n == 0) continue;
+    SapLaunch a;
+    a.lats = L;
+    a.items = it.d.as<WorkItem>();
+    a.nitems = it.n;
+    a.colour = colour;
+    a.nmr = nmr;
+    a.rho = rho.data();
+    a.rho_sc = rho.scale();
+    a.z = z.data();
+    a.z_sc = z.scale();
+    a.psi = psi.data();
+    a.psi_sc = psi.scale();
+    a.skip = skip;
+    a.first = first;
+    a.border = border;
+    a.write_rho = wrho;
+    a.write_z = wz;
+    a.cache = sap_cache_mode(B, it.n);
+    a.uniform_bvol = bv;
+    a.odd_rho = odd_rho;
+    // (with the operator cached the launch has one work-group per CU, and the entries'
+    // extra barrier costs more than the divergent per-site update: measured at 16^3 x 32)
+    a.border_entries = (eo && !a.cache) ? bentries : 0;
+    a.eo_rows = 2 * ((bv + 1) / 2);
+    if (eo)
+      launch_sap_eo(prec, nr, a, persistent_grid(it.n, 4), bv, st);
+    else if (is16(prec) && nr == 2 && bv == 256)
+      launch_sap_mr_lds(prec, nr, a, persistent_grid(it.n, 1), st);
+    else
+      launch_sap_mr(prec, nr, a, persistent_grid(it.n, 4), ((bv + 63) / 64) * 64, st);
+  }
 }
 
 // ncy Schwarz cycles on rho (source), accumulating psi
@@ -703,10 +772,10 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   // everything a captured cycle touches must exist before capture starts
   B.lats(P_F64, nullptr);
   B.lats(s.sap_prec, nullptr, s.eo != 0);
-  B.items_dirac(1);
-  B.items_dirac(s.nr_d);
-  B.items_sap(0, s.nr_s);
-  B.items_sap(1, s.nr_s);
+  for (int nr : {1, s.nr_d})
+    for (int sel = 0; sel < 3; ++sel) B.items_dirac(nr, sel);
+  for (int bv : B.bvols())
+    for (int c = 0; c < 2; ++c) B.items_sap(c, s.nr_s, bv);
   HIPCK(hipDeviceSynchronize());
 }
 
@@ -1258,6 +1327,7 @@ static void layout(wc_ctx* c, const int* block, hipStream_t st) {
 
 wc_ctx::~wc_ctx() {
   batches.clear();
+  wc::drop_multi_batches(this);
   if (cap) (void)hipStreamDestroy(cap);
 }
 
@@ -1346,6 +1416,11 @@ int wc_create_clover(wc_ctx* c, double m0, double csw, void* stream) {
     }
     for (auto& kv : c->batches)
       for (int p = 0; p < 4; ++p) kv.second->have_lats[p] = false;
+    for (auto& kv : multi_batches()) {
+      const auto& cs = kv.first.first;
+      if (std::find(cs.begin(), cs.end(), c) != cs.end())
+        for (int p = 0; p < 4; ++p) kv.second->have_lats[p] = false;
+    }
   });
 }
 
@@ -1533,6 +1608,12 @@ int wc_sap(wc_ctx* c, void* psi, const void* eta, int nrhs, int ncy, int nmr, in
   });
 }
 
+// the cached batch of these lattices (argument checks first: a bad list caches nothing)
+static Batch* batch_for(const std::vector<wc_ctx*>& cs, const std::vector<int>& ns) {
+  for (size_t i = 0; i < cs.size(); ++i) require(cs[i] && ns[i] >= 1, WC_ERR_ARG, "bad lattice argument");
+  return cs.size() == 1 ? &ctx_batch(cs[0], ns[0]) : &multi_batch(cs, ns);
+}
+
 // kdefl < 0: FGCR; kdefl >= 0: FGMRES-DR keeping kdefl harmonic Ritz vectors
 static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<int>& nrhs, void* const* x,
                             const void* const* b, const wc_solver_params* p, wc_solver_stats* st_out, void* stream,
@@ -1635,7 +1716,10 @@ int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const voi
   }
   std::vector<wc_ctx*> cs(ctxs, ctxs + nlat);
   std::vector<int> ns(nrhs, nrhs + nlat);
-  return solve_batch_impl(cs, ns, x, b, p, st, stream, nullptr);
+  Batch* B = nullptr;
+  int rc = guarded([&] { B = batch_for(cs, ns); });
+  if (rc != WC_OK) return rc;
+  return solve_batch_impl(cs, ns, x, b, p, st, stream, B);
 }
 
 int wc_fgmres_dr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
@@ -1646,7 +1730,10 @@ int wc_fgmres_dr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, cons
   }
   std::vector<wc_ctx*> cs(ctxs, ctxs + nlat);
   std::vector<int> ns(nrhs, nrhs + nlat);
-  return solve_batch_impl(cs, ns, x, b, p, st, stream, nullptr, kdefl);
+  Batch* B = nullptr;
+  int rc = guarded([&] { B = batch_for(cs, ns); });
+  if (rc != WC_OK) return rc;
+  return solve_batch_impl(cs, ns, x, b, p, st, stream, B, kdefl);
 }
 
 int wc_link_grad(wc_ctx* c, void* G, const void* Y, const void* X, int nrhs, double coef, void* stream) {

@@ -24,7 +24,7 @@ struct DiracLaunch {
   const int* skip;     // if set: systems with skip != 0 are not written
   int dagger;          // apply gamma5 D gamma5
   int block;           // Dirichlet-block operator instead of the full one
-  int stage;           // every lattice has 256-site tiles: stage each tile's input in LDS
+  int stage;           // the items' lattices have 256-site tiles: stage each tile's input in LDS
   int in_prec;         // storage precision of `in` (may differ from the launch's only for FP64)
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);

@@ -112,6 +112,46 @@ def test_fgcr_uneven_batch():
             k += 1
 
 
+def test_uneven_batch_kept_between_calls_and_dropped_with_its_lattices():
+    """A batch of several lattices keeps its fields and captured cycles between calls (the
+    second call's solution equals the first bit for bit; new sources are solved), and a
+    block change of one lattice or the loss of one drops it: the next call builds a new
+    batch and solves correctly (true residuals by the oracle's D)."""
+    import gc
+
+    import paper_1109_4279_amd as wc
+    m0, csw = -0.1, 1.0
+    specs = [((8, 4, 4, 4), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4))]
+    lats = [lattice(d, blk, m0, csw, seed=synth.GAUGE_SEED + i) for i, (d, blk) in enumerate(specs)]
+    kw = dict(tol=1e-10, sap_prec="f32", eo=1)
+
+    def sources(seed):
+        return [synth.gaussian_spinor(d, nrhs=2, seed=seed + i) for i, (d, _) in enumerate(specs)]
+
+    def check(xs, bs):
+        for i, (dims, _) in enumerate(specs):
+            U = synth.gauge_field(dims, seed=synth.GAUGE_SEED + i)
+            A = dirac.clover_matrix(U, m0, csw)
+            x = to_np(xs[i])
+            for r in range(2):
+                assert dirac.norm(bs[i][r] - dirac.apply_D(U, A, x[r])) / dirac.norm(bs[i][r]) <= 1e-10
+
+    b1 = sources(synth.RHS_SEED)
+    x1, _ = wc.solve_batch(lats, [to_dev(b) for b in b1], **kw)
+    x2, _ = wc.solve_batch(lats, [to_dev(b) for b in b1], **kw)
+    check(x1, b1)
+    for a, b in zip(x1, x2):
+        assert np.array_equal(to_np(a), to_np(b))
+    b2 = sources(synth.RHS_SEED + 10)
+    check(wc.solve_batch(lats, [to_dev(b) for b in b2], **kw)[0], b2)
+    lats[1].set_block((2, 2, 2, 2))
+    check(wc.solve_batch(lats, [to_dev(b) for b in b2], **kw)[0], b2)
+    del lats[0]
+    gc.collect()
+    lats.insert(0, lattice(specs[0][0], specs[0][1], m0, csw, seed=synth.GAUGE_SEED))
+    check(wc.solve_batch(lats, [to_dev(b) for b in b2], **kw)[0], b2)
+
+
 def test_graph_replay_equals_eager():
     dims, block = (8, 4, 4, 4), (2, 2, 2, 2)
     lat = lattice(dims, block)
