@@ -289,9 +289,15 @@ void launch_clover_build(const Geom& g, const void* links64, double m0, double c
 
 // Clover field of the even/odd block solver: A(x) on even sites, A(x)^-1 on odd sites
 // (parity = sum of the global coordinates mod 2), FP64, same storage as the clover term.
-// One thread per (site, chiral block).  A 6x6 Hermitian block is inverted by Gauss-Jordan
-// elimination of [A | 1] with partial pivoting (compare-and-swap of rows, so every index
-// is a compile-time constant); the result is re-symmetrised to the stored Hermitian form.
+// One thread per (site, chiral block).  A 6x6 Hermitian block is inverted in place by
+// Gauss-Jordan elimination with partial pivoting: at step k the rows k..5 are compared and
+// swapped into pivot order (selects, so every index is a compile-time constant, and a
+// record of which original row each position holds), row k is scaled by the inverse
+// pivot, whose column then holds the inverse's entries, and row k is eliminated from the
+// others.  With P the accumulated row permutation the array then holds (P A)^-1 = A^-1 P^T,
+// so column i of it is column prow[i] of A^-1; the stored upper triangle picks its entries
+// through that record and is re-symmetrised.  The 36 complex entries fit the registers
+// (an augmented [A | 1] of 72 did not, and spilled to scratch memory).
 __global__ __launch_bounds__(WG) void k_clover_eo(Geom g, const double2* c64, double2* out) {
   const int i = blockIdx.x * WG + threadIdx.x;
   if (i >= 2 * g.V) return;
@@ -310,11 +316,8 @@ __global__ __launch_bounds__(WG) void k_clover_eo(Geom g, const double2* c64, do
     for (int k = 0; k < 18; ++k) dst[(size_t)k * g.V] = src[(size_t)k * g.V];
     return;
   }
-  cplx<double> M[6][12];
-#pragma unroll
-  for (int r = 0; r < 6; ++r)
-#pragma unroll
-    for (int c = 0; c < 12; ++c) M[r][c] = {c == r + 6 ? 1.0 : 0.0, 0.0};
+  cplx<double> M[6][6];
+  int prow[6];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double2 v = src[(size_t)k * g.V];
@@ -333,41 +336,61 @@ __global__ __launch_bounds__(WG) void k_clover_eo(Geom g, const double2* c64, do
       }
   }
 #pragma unroll
+  for (int r = 0; r < 6; ++r) prow[r] = r;
+#pragma unroll
   for (int k = 0; k < 6; ++k) {
 #pragma unroll
     for (int r = k + 1; r < 6; ++r) {
       const double a = M[r][k].re * M[r][k].re + M[r][k].im * M[r][k].im;
       const double b = M[k][k].re * M[k][k].re + M[k][k].im * M[k][k].im;
       const bool sw = a > b;
+      // (selects on the scalar parts: a select between two array elements would take their
+      // addresses and keep the array out of registers)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const cplx<double> t = M[k][c];
-        M[k][c] = sw ? M[r][c] : t;
-        M[r][c] = sw ? t : M[r][c];
+      for (int c = 0; c < 6; ++c) {
+        const double kr = M[k][c].re, ki = M[k][c].im, rr = M[r][c].re, ri = M[r][c].im;
+        M[k][c] = {sw ? rr : kr, sw ? ri : ki};
+        M[r][c] = {sw ? kr : rr, sw ? ki : ri};
       }
+      const int t = prow[k];
+      prow[k] = sw ? prow[r] : t;
+      prow[r] = sw ? t : prow[r];
     }
     const cplx<double> p = M[k][k];
     const double den = p.re * p.re + p.im * p.im;
     const cplx<double> inv = {p.re / den, -p.im / den};
+    M[k][k] = {1.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 12; ++c) M[k][c] = inv * M[k][c];
+    for (int c = 0; c < 6; ++c) M[k][c] = inv * M[k][c];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
       if (r == k) continue;
       const cplx<double> f = M[r][k];
+      M[r][k] = {0.0, 0.0};
 #pragma unroll
-      for (int c = 0; c < 12; ++c) M[r][c] = M[r][c] - f * M[k][c];
+      for (int c = 0; c < 6; ++c) M[r][c] = M[r][c] - f * M[k][c];
     }
   }
+  // entry (r, j) of A^-1 is M[r][i] with prow[i] == j
+  auto inv_at = [&](int r, int j) {
+    double re = 0.0, im = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) dst[(size_t)k * g.V] = make_double2(M[2 * k][2 * k + 6].re, M[2 * k + 1][2 * k + 7].re);
+    for (int c = 0; c < 6; ++c) {
+      const bool hit = prow[c] == j;
+      re = hit ? M[r][c].re : re;
+      im = hit ? M[r][c].im : im;
+    }
+    return cplx<double>{re, im};
+  };
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dst[(size_t)k * g.V] = make_double2(inv_at(2 * k, 2 * k).re, inv_at(2 * k + 1, 2 * k + 1).re);
   {
     int k = 0;
 #pragma unroll
     for (int r = 0; r < 6; ++r)
 #pragma unroll
       for (int c = r + 1; c < 6; ++c, ++k) {
-        const cplx<double> up = M[r][c + 6], lo = M[c][r + 6];
+        const cplx<double> up = inv_at(r, c), lo = inv_at(c, r);
         dst[(size_t)(3 + k) * g.V] = make_double2(0.5 * (up.re + lo.re), 0.5 * (up.im - lo.im));
       }
   }
