@@ -560,7 +560,9 @@ def profile_run(wc, torch, dev):
     lat = wc.Lattice(torch.from_numpy(synth.gauge_field(C4_DIMS)).to(dev), block=BLOCK, m0=M0, csw=CSW)
     pts = torch.from_numpy(synth.point_sources(C4_DIMS)).to(dev)
     storage = os.environ.get("WC_BENCH_STORAGE", "bf16")
-    lat.autotune(12, prec=storage)
+    tiles = lat.autotune(12, prec=storage)
+    _TILES[(id(lat), storage)] = tiles[0]
+    _TILES[(id(lat), "f64")] = tiles[1]
     p = params(wc, storage, True)
     lat.solve(pts, p)
     (_, st), ms = sync_time(torch, lambda: lat.solve(pts, p))
@@ -569,6 +571,30 @@ def profile_run(wc, torch, dev):
     print(json.dumps({"profile": "24^3x48 x 12 point sources", "storage": storage, "solve_ms": ms,
                       "iters": max(s["iters"] for s in st), "half_sweep_ms": rf["launch_ms"],
                       "dirac_12rhs": dw}), flush=True)
+
+
+def counter_summary(csv_path, out_md, command, match="k_sap_eo", last=20):
+    """Markdown table of a rocprofv3 --pmc run: for each kernel whose name contains `match`,
+    the mean of every counter over its last `last` dispatches (the timing loops of
+    `bench.py --profile`)."""
+    import csv
+    rows = [r for r in csv.DictReader(open(csv_path)) if match in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    agg = {}
+    for r in rows:
+        k = r["Kernel_Name"].replace("void ", "").replace("wc::", "").split("(")[0]
+        agg.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({c for d in agg.values() for c in d})
+    lines = [f"Command: `{command}`", "", "| kernel | " + " | ".join(names) + " |",
+             "|---|" + "---|" * len(names)]
+    for k, d in agg.items():
+        vals = []
+        for c in names:
+            v = d.get(c, [])[-last:]
+            vals.append(f"{sum(v) / len(v):.6g}" if v else "")
+        lines.append(f"| `{k}` | " + " | ".join(vals) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    return {k: {c: sum(v[-last:]) / len(v[-last:]) for c, v in d.items()} for k, d in agg.items()}
 
 
 def profile_summary(stats_dir, out_md, command, traffic_json=None, top=16):
@@ -603,6 +629,10 @@ def profile_summary(stats_dir, out_md, command, traffic_json=None, top=16):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
         summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--counter-summary":
+        # --counter-summary CSV OUT_MD COMMAND [MATCH]
+        counter_summary(sys.argv[2], sys.argv[3], sys.argv[4], *(sys.argv[5:6]))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--profile-summary":
         # --profile-summary STATS_DIR OUT_MD COMMAND [TRAFFIC_JSON]

@@ -117,3 +117,21 @@ def test_profile_summary(tmp_path):
     assert md.startswith("Command: `rocprofv3 ... -- python3 bench.py --profile`")
     assert lines[4] == "| `k_sap_eo<3, 1, false>` | 25 | 50.00 | 40.00 | 1.250 | 90.0 | 2500.0 |"
     assert lines[5] == "| `k_gs_dots` | 2 | 1.00 | 1.00 | 0.002 | 10.0 |  |"
+
+
+def test_counter_summary(tmp_path):
+    """Per-counter means over the last dispatches of the matching kernels."""
+    rows = []
+    for i in range(25):
+        rows.append(("void wc::k_sap_eo<3, 1, false>(wc::SapLaunch)", "SQ_INSTS_VALU", 100.0 if i < 5 else 10.0))
+        rows.append(("void wc::k_sap_eo<3, 1, false>(wc::SapLaunch)", "GRBM_GUI_ACTIVE", 7.0))
+        rows.append(("wc::k_gs_dots(wc::VecLaunch)", "SQ_INSTS_VALU", 1.0))
+    with open(tmp_path / "c.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+    rec = bench.counter_summary(str(tmp_path / "c.csv"), str(tmp_path / "c.md"), "cmd")
+    assert rec == {"k_sap_eo<3, 1, false>": {"SQ_INSTS_VALU": 10.0, "GRBM_GUI_ACTIVE": 7.0}}
+    md = (tmp_path / "c.md").read_text()
+    assert "| `k_sap_eo<3, 1, false>` | 7 | 10 |" in md
