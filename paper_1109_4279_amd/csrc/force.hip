@@ -78,7 +78,9 @@ WC_D void spin(const double2* F, const Lat& g, int r, int s, zc (*v)[3]) {
 WC_D void sigma_munu(int r, int s, zc (*sg)[4]) {
   const zc Z = {0, 0}, O = {1, 0}, I = {0, 1};
   zc pauli[3][2][2] = {{{Z, O}, {O, Z}}, {{Z, -I}, {I, Z}}, {{O, Z}, {Z, -O}}};
+#pragma unroll
   for (int i = 0; i < 4; ++i)
+#pragma unroll
     for (int j = 0; j < 4; ++j) sg[i][j] = Z;
   int l;
   double up, lo;
@@ -94,7 +96,9 @@ WC_D void sigma_munu(int r, int s, zc (*sg)[4]) {
     up = lo = -eps;
     l = l - 1;
   }
+#pragma unroll
   for (int i = 0; i < 2; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j) {
       sg[i][j] = up * pauli[l][i][j];
       sg[2 + i][2 + j] = lo * pauli[l][i][j];
@@ -109,6 +113,7 @@ __global__ __launch_bounds__(WG) void k_force_xi(Lat g, const double2* Y, const 
                                                  double2* xi) {
   const int s = blockIdx.x * WG + threadIdx.x;
   if (s >= g.V) return;
+#pragma unroll
   for (int p = 0; p < 6; ++p) {
     zc sg[4][4];
     sigma_munu(PLANE_R[p], PLANE_S[p], sg);
@@ -117,10 +122,14 @@ __global__ __launch_bounds__(WG) void k_force_xi(Lat g, const double2* Y, const 
       zc x[4][3], y[4][3];
       spin(X, g, r, s, x);
       spin(Y, g, r, s, y);
+#pragma unroll
       for (int si = 0; si < 4; ++si)
+#pragma unroll
         for (int ti = 0; ti < 4; ++ti) {
           if (sg[si][ti].re == 0.0 && sg[si][ti].im == 0.0) continue;
+#pragma unroll
           for (int a = 0; a < 3; ++a)
+#pragma unroll
             for (int b = 0; b < 3; ++b) {
               zc t = sg[si][ti] * x[ti][a];
               cmac(G.m[a][b], t, conj(y[si][b]));
@@ -128,7 +137,9 @@ __global__ __launch_bounds__(WG) void k_force_xi(Lat g, const double2* Y, const 
         }
     }
     double2* o = xi + ((size_t)p * g.V + s) * 9;
+#pragma unroll
     for (int a = 0; a < 3; ++a)
+#pragma unroll
       for (int b = 0; b < 3; ++b) {
         zc h = G.m[a][b] + conj(G.m[b][a]);
         zc v = (csw / 16.0) * timesI(h);
@@ -137,9 +148,11 @@ __global__ __launch_bounds__(WG) void k_force_xi(Lat g, const double2* Y, const 
   }
 }
 
-// the four leaves at y in the (r, s) plane, oriented r -> s, as (axis: 0 = r, 1 = s; step)
-__constant__ int LEAF_AX[4][4] = {{0, 1, 0, 1}, {1, 0, 1, 0}, {0, 1, 0, 1}, {1, 0, 1, 0}};
-__constant__ int LEAF_SG[4][4] = {{1, 1, -1, -1}, {1, -1, -1, 1}, {-1, -1, 1, 1}, {-1, 1, 1, -1}};
+// the four leaves at y in the (r, s) plane, oriented r -> s, as (axis: 0 = r, 1 = s; step);
+// compile-time tables, so that the unrolled loops below index every array with constants
+// and the arrays stay in registers
+constexpr int LEAF_AX[4][4] = {{0, 1, 0, 1}, {1, 0, 1, 0}, {0, 1, 0, 1}, {1, 0, 1, 0}};
+constexpr int LEAF_SG[4][4] = {{1, 1, -1, -1}, {1, -1, -1, 1}, {-1, -1, 1, 1}, {-1, 1, 1, -1}};
 
 // pass 2: K_mu(x) (hopping + clover), then the requested output
 __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, const double2* Y, const double2* X,
@@ -149,6 +162,7 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
   if (s >= g.V) return;
   int x[4];
   coords(g, s, x);
+#pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     Mat K = mz();
     int xp[4] = {x[0], x[1], x[2], x[3]};
@@ -164,6 +178,7 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
       spin(Y, g, r, sp, Yp);
       // (1 - g_mu) Y(x) and (1 + g_mu) Y(x + mu) in the chiral basis
       zc Pm[4][3], Pp[4][3];
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
         zc u0 = Ys[0][a], u1 = Ys[1][a], l0 = Ys[2][a], l1 = Ys[3][a];
         zc v0 = Yp[0][a], v1 = Yp[1][a], w0 = Yp[2][a], w1 = Yp[3][a];
@@ -178,14 +193,18 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
         gam(u0, u1, l0, l1, gm);
         gam(v0, v1, w0, w1, gp);
         zc ys[4] = {u0, u1, l0, l1}, yp[4] = {v0, v1, w0, w1};
+#pragma unroll
         for (int t = 0; t < 4; ++t) {
           Pm[t][a] = ys[t] - gm[t];
           Pp[t][a] = yp[t] + gp[t];
         }
       }
+#pragma unroll
       for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int b = 0; b < 3; ++b) {
           zc acc = {0.0, 0.0};
+#pragma unroll
           for (int t = 0; t < 4; ++t) {
             cmac(acc, Xp[t][a], conj(Pm[t][b]));
             cmac(acc, Pp[t][a], conj(Xs[t][b]));
@@ -195,48 +214,62 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
     }
     // clover part: the planes that contain mu, every leaf position holding U_mu(x)
     if (csw != 0.0) {
+#pragma unroll
       for (int p = 0; p < 6; ++p) {
         const int pr = PLANE_R[p], ps = PLANE_S[p];
         if (pr != mu && ps != mu) continue;
         const int ax_mu = (pr == mu) ? 0 : 1;
+#pragma unroll
         for (int lf = 0; lf < 4; ++lf) {
           // offsets of each step's link from the leaf origin y
           int off[4][4], pos[4] = {0, 0, 0, 0}, dir[4];
           bool dg[4];
+#pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int d = LEAF_AX[lf][j] == 0 ? pr : ps;
             dir[j] = d;
             if (LEAF_SG[lf][j] > 0) {
+#pragma unroll
               for (int m = 0; m < 4; ++m) off[j][m] = pos[m];
               pos[d] += 1;
               dg[j] = false;
             } else {
               pos[d] -= 1;
+#pragma unroll
               for (int m = 0; m < 4; ++m) off[j][m] = pos[m];
               dg[j] = true;
             }
           }
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (LEAF_AX[lf][i] != ax_mu) continue;
             int y[4];
+#pragma unroll
             for (int m = 0; m < 4; ++m) y[m] = x[m] - off[i][m];
             Mat W[4];
+#pragma unroll
             for (int j = 0; j < 4; ++j) {
               int z[4];
+#pragma unroll
               for (int m = 0; m < 4; ++m) z[m] = y[m] + off[j][m];
               Mat l = link(U, g, dir[j], lex(g, z));
               W[j] = dg[j] ? mdag(l) : l;
             }
             Mat Xi;
             const double2* xp2 = xi + ((size_t)p * g.V + lex(g, y)) * 9;
+#pragma unroll
             for (int k = 0; k < 9; ++k) Xi.m[k / 3][k % 3] = {xp2[k].x, xp2[k].y};
             Mat R;
             bool have = false;
+#pragma unroll
             for (int j = i + 1; j < 4; ++j) { R = have ? mmul(R, W[j]) : W[j]; have = true; }
             R = have ? mmul(R, Xi) : Xi;
+#pragma unroll
             for (int j = 0; j < i; ++j) R = mmul(R, W[j]);
             if (dg[i]) R = mdag(R);
+#pragma unroll
             for (int a = 0; a < 3; ++a)
+#pragma unroll
               for (int b = 0; b < 3; ++b) K.m[a][b] = K.m[a][b] + R.m[a][b];
           }
         }
@@ -244,7 +277,9 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
     }
     double2* o = out + ((size_t)mu * g.V + s) * 9;
     if (out_kind == 0) {  // torch-convention gradient G = coef * K^dag
+#pragma unroll
       for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int b = 0; b < 3; ++b) {
           zc v = coef * conj(K.m[b][a]);
           o[a * 3 + b] = make_double2(v.re, v.im);
@@ -252,11 +287,16 @@ __global__ __launch_bounds__(WG) void k_force_link(Lat g, const double2* U, cons
     } else {  // Lie-algebra force TA(U K) * coef
       Mat UK = mmul(link(U, g, mu, s), K);
       Mat A;
+#pragma unroll
       for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int b = 0; b < 3; ++b) A.m[a][b] = 0.5 * (UK.m[a][b] - conj(UK.m[b][a]));
       zc tr = A.m[0][0] + A.m[1][1] + A.m[2][2];
+#pragma unroll
       for (int a = 0; a < 3; ++a) A.m[a][a] = A.m[a][a] - (1.0 / 3.0) * tr;
+#pragma unroll
       for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int b = 0; b < 3; ++b) {
           zc v = coef * A.m[a][b];
           o[a * 3 + b] = make_double2(v.re, v.im);
