@@ -461,9 +461,9 @@ def near_critical_quenched(wc, torch, dev, block):
     field at beta = 6.0 (Wilson action; cold start, 20 x (1 heatbath + 4 overrelaxation)
     sweeps on the GPU), c_sw = 1.769, its critical mass estimated by shift-invert Arnoldi (two
     stages, the second 0.02 above the first estimate), then FGCR(16), FGCR(32) and
-    FGMRES-DR(32, 10) on a Gaussian source at 0.02 and 0.005 above it (FP32 even/odd SAP,
-    FP64 outer, tol 1e-10, maxit 3000): the regime of Fig. 1, where restarted GCR slows down
-    and deflated restarts keep the low modes."""
+    FGMRES-DR(32, 10) on a Gaussian source at 0.02, 0.005 and 0.001 above it (FP32 even/odd
+    SAP, FP64 outer, tol 1e-10, maxit 3000): the regime of Fig. 1, where restarted GCR slows
+    down and deflated restarts keep the low modes."""
     import synth
     from synth import quenched
     t0 = time.perf_counter()
@@ -481,9 +481,11 @@ def near_critical_quenched(wc, torch, dev, block):
                             "estimate": c2}
     b = torch.from_numpy(synth.gaussian_spinor(C2_DIMS)).to(dev)
     kw = dict(ncy=NCY, nmr=NMR, tol=TOL, sap_prec="f32", eo=1, maxit=3000)
-    for dm in (0.02, 0.005):
+    lam2 = [complex(a, bb) for a, bb in l2]
+    for dm in (0.02, 0.005, 0.001):
         lat = wc.Lattice(U, block=block, m0=c2 + dm, csw=QUENCHED_CSW)
-        r = {"m0": c2 + dm}
+        # the estimated smallest |eigenvalue| of D at this mass (the spectrum shifted by m0)
+        r = {"m0": c2 + dm, "smallest_abs_eigenvalue": min(abs(z + (c2 + dm) - (c1 + 0.02)) for z in lam2)}
 
         def run(name, f):
             f()
