@@ -114,8 +114,8 @@ void wc_default_params(wc_solver_params* p);
  * WC_OPT_SAP_CACHE    -1 automatic (default): the block solver keeps the block operator in
  *                     registers when a launch has at most two work items per CU;
  *                     0 reload it in every phase; 1 keep it in registers (FP32-math kernels).
- * WC_OPT_DIRAC_STAGE  -1 automatic (default): FP64 D_w stages each 256-site tile's input
- *                     in LDS; 0 never; 1 also for FP32 and 16-bit storage.
+ * WC_OPT_DIRAC_STAGE  -1 automatic (default) and 1: D_w stages each 256-site tile's input
+ *                     in LDS (lattices with 256-site blocks, tiles that fit); 0 never.
  * Both select kernels only; results agree to rounding.  Errors: WC_ERR_ARG. */
 typedef enum { WC_OPT_SAP_CACHE = 0, WC_OPT_DIRAC_STAGE = 1 } wc_option;
 int wc_set_option(wc_ctx* ctx, int option, int value);

@@ -38,6 +38,23 @@ struct WorkItem {
   int nr;
 };
 
+// Work items and lattice descriptors are read through the constant address space, word by
+// word: with a uniform address the compiler then loads them with scalar loads into scalar
+// registers once per item, instead of vector loads that it repeats at every use when
+// registers run short (D_w: 12-rhs FP64 1.80 -> 1.67 ms, one 16-bit rhs per lane 0.77 ->
+// 0.52 ms at 24^3 x 48; the even/odd block solver, short of scalar registers, got slower
+// with it and keeps its vector loads).
+template <class T> WC_D T load_uniform(const T* p, int i) {
+  static_assert(sizeof(T) % 4 == 0, "whole words only");
+  typedef const __attribute__((address_space(4))) uint32_t* cword_t;
+  const cword_t src = (cword_t)(p + i);
+  T out;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
 // Map a work index so that the items run by one XCD (work-groups are dealt to
 // the 8 XCDs round-robin) form a contiguous range, keeping neighbouring sites
 // in one L2.
