@@ -628,6 +628,27 @@ def profile_summary(stats_dir, out_md, command, traffic_json=None, top=16):
     return lines
 
 
+def profile_dirac_run(wc, torch, dev):
+    """A short run for profilers of single-rhs D_w at 32^3 x 64 in every storage precision
+    (the 1 GiB calibration copy first, then 30 launches per precision); prints the HIP-event
+    times and the algorithmic bytes per launch."""
+    import synth
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    lat = wc.Lattice(torch.from_numpy(synth.gauge_field(C3_DIMS)).to(dev), block=BLOCK, m0=M0, csw=CSW)
+    V = 2097152
+    out = {}
+    for prec in ("f64", "f32", "f16", "bf16"):
+        ms = lat.bench_dirac(prec=prec, nrhs=1, iters=30)
+        out[prec] = {"ms": ms, "alg_bytes_per_launch": dw_bytes(prec) * V,
+                     "frac_hbm": dw_bytes(prec) * V / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    print(json.dumps({"profile": "D_w 32^3x64, 1 rhs", "dirac": out}), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
         summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -647,6 +668,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the headline step and its roofline")
     ap.add_argument("--profile", action="store_true", help="short run for profilers (no tuning, no extras)")
+    ap.add_argument("--profile-dirac", action="store_true", help="short profiler run of single-rhs D_w at 32^3x64")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (sharding the lattice "
@@ -662,6 +684,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.profile:
         profile_run(wc, torch, dev)
+        return
+    if args.profile_dirac:
+        profile_dirac_run(wc, torch, dev)
         return
     V = 663552
     lat = wc.Lattice(torch.from_numpy(synth.gauge_field(C4_DIMS)).to(dev), block=BLOCK, m0=M0, csw=CSW)
