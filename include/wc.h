@@ -192,8 +192,13 @@ int wc_fgmres_dr_solve(wc_ctx* ctx, void* x, const void* b, int nrhs, const wc_s
                        wc_solver_stats* st, void* stream);
 
 /* The same for nlat lattices of different sizes solved together: every kernel of the
- * solve is one launch over all lattices and right-hand sides.  x[i], b[i] are the
- * lattice-i arrays with nrhs[i] right-hand sides; st receives sum(nrhs) entries. */
+ * solve is one launch over all lattices and right-hand sides (the block solver one per
+ * block volume among them).  x[i], b[i] are the lattice-i arrays with nrhs[i] right-hand
+ * sides; st receives sum(nrhs) entries.  The work fields and captured cycles of a list of
+ * lattices and rhs counts are kept for the next call with the same list (device memory of
+ * about (2 nkv + 6) FP64 fields of sum(nrhs) right-hand sides), until one of its contexts
+ * changes its block layout or is destroyed; such a call counts as a call on every one of
+ * its contexts for the concurrency rule above. */
 int wc_fgcr_solve_batch(wc_ctx* const* ctxs, int nlat, void* const* x, const void* const* b, const int* nrhs,
                         const wc_solver_params* p, wc_solver_stats* st, void* stream);
 
