@@ -198,22 +198,72 @@ def cpu_baseline(iters, restarts, workers):
     return rec
 
 
-def measured_traffic(kernel, path):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    record at `path`, or None when the kernel sources changed since it was taken."""
+def csrc_sha256():
+    """Digest of the kernel sources (every .hip and .h under csrc/), stored with each counter
+    record so that a record taken on other kernels is not used."""
     import hashlib
-    try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", path)))
-    except (OSError, ValueError):
-        return None
     src = os.path.join(ROOT, "paper_1109_4279_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(src)):
         if f.endswith((".hip", ".h")):
             h.update(open(os.path.join(src, f), "rb").read())
-    if rec.get("csrc_sha256") != h.hexdigest() or kernel not in rec.get("kernels", {}):
+    return h.hexdigest()
+
+
+def _current_record(path, kernel):
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", path)))
+    except (OSError, ValueError):
         return None
-    return rec["kernels"][kernel]["bytes_per_launch"]
+    if rec.get("csrc_sha256") != csrc_sha256() or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]
+
+
+def measured_traffic(kernel, path):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record at `path`, or None when the kernel sources changed since it was taken."""
+    r = _current_record(path, kernel)
+    return None if r is None else r["bytes_per_launch"]
+
+
+def measured_valu(kernel, path):
+    """VALU occupancy of `kernel` from the committed SQ counter record at `path` (see
+    valu_record), or None when the kernel sources changed since it was taken."""
+    return _current_record(path, kernel)
+
+
+def valu_record(csv_path, out_json, kernel="k_sap_eo<3, 1, false>", simds=1024, xcds=8):
+    """VALU occupancy of the block solver from a rocprofv3 --pmc SQ_INSTS_VALU GRBM_GUI_ACTIVE
+    run of `bench.py --profile`, whose last timing loops are 20+ launches without MR steps
+    and then 20+ with them: SQ_INSTS_VALU x 4 cycles per wave64 instruction over the SIMDs
+    and the launch's cycles per XCD (GRBM_GUI_ACTIVE / xcds), for the launch with MR steps,
+    the one without (set-up, odd half, stores) and their difference (the MR steps)."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        short = r["Kernel_Name"].replace("void ", "").replace("wc::", "").split("(")[0]
+        if short == kernel:
+            per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    ids = sorted(per)
+    last = per[ids[-1]]["SQ_INSTS_VALU"]
+    with_mr = ids[-20:]
+    without = [i for i in ids if abs(per[i]["SQ_INSTS_VALU"] - last) > 0.01 * last][-20:]
+
+    def mean(sel, c):
+        return sum(per[i][c] for i in sel) / len(sel)
+
+    def busy(v, g):
+        return v * 4 / (simds * g / xcds)
+
+    v4, g4 = mean(with_mr, "SQ_INSTS_VALU"), mean(with_mr, "GRBM_GUI_ACTIVE")
+    v0, g0 = mean(without, "SQ_INSTS_VALU"), mean(without, "GRBM_GUI_ACTIVE")
+    rec = {"csrc_sha256": csrc_sha256(),
+           "command": "rocprofv3 --pmc SQ_INSTS_VALU ... GRBM_GUI_ACTIVE --output-format csv -- python bench.py --profile",
+           "kernels": {kernel: {"valu_busy_launch": busy(v4, g4), "valu_busy_without_mr_steps": busy(v0, g0),
+                                "valu_busy_mr_steps": busy(v4 - v0, g4 - g0), "valu_instructions_per_launch": v4}}}
+    json.dump(rec, open(out_json, "w"), indent=1)
+    return rec
 
 
 def sync_time(torch, f):
@@ -510,7 +560,6 @@ def summarise_pmc(fetch_csv, write_csv, out_json, kernels_of_interest=None):
     run's 1 GiB device copy (1 GiB read, 1 GiB written); each kernel's figure is the mean of
     its last 20 dispatches (the timing loop whose duration bench.py reports)."""
     import csv
-    import hashlib
 
     def per_kernel(path, name):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == name]
@@ -527,11 +576,6 @@ def summarise_pmc(fetch_csv, write_csv, out_json, kernels_of_interest=None):
     fetch = {k: v[-20:] for k, v in fetch_all.items()}
     write = {k: v[-20:] for k, v in write_all.items()}
     cf, cw = gib / copy_f, gib / copy_w
-    src = os.path.join(ROOT, "paper_1109_4279_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(src, f), "rb").read())
     kernels = {}
     for k in fetch:
         if "wc::" not in k or k not in write:
@@ -541,7 +585,7 @@ def summarise_pmc(fetch_csv, write_csv, out_json, kernels_of_interest=None):
         wb = cw * sum(write[k]) / len(write[k])
         kernels[short] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
                           "launches": len(fetch[k])}
-    rec = {"csrc_sha256": h.hexdigest(), "fetch_scale": cf, "write_scale": cw,
+    rec = {"csrc_sha256": csrc_sha256(), "fetch_scale": cf, "write_scale": cw,
            "command": "rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv -- python bench.py --profile",
            "kernels": kernels}
     json.dump(rec, open(out_json, "w"), indent=1)
@@ -653,6 +697,10 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarise-pmc":
         summarise_pmc(sys.argv[2], sys.argv[3], sys.argv[4])
         return
+    if len(sys.argv) > 1 and sys.argv[1] == "--valu-record":
+        # --valu-record CSV OUT_JSON
+        valu_record(sys.argv[2], sys.argv[3])
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--counter-summary":
         # --counter-summary CSV OUT_MD COMMAND [MATCH]
         counter_summary(sys.argv[2], sys.argv[3], sys.argv[4], *(sys.argv[5:6]))
@@ -732,6 +780,7 @@ def main():
                                f"of 24^3x48 x 12 rhs, {NMR} steps", tile=etile)
     pcode = {"f32": 1, "f16": 2, "bf16": 3}[storage]
     roofline["traffic"] = measured_traffic(f"k_sap_eo<{pcode}, {etile}, false>", "traffic_24c48.json")
+    roofline["valu_occupancy"] = measured_valu(f"k_sap_eo<{pcode}, {etile}, false>", "valu_24c48.json")
 
     extras = {}
     if not args.no_extras:

@@ -135,3 +135,34 @@ def test_counter_summary(tmp_path):
     assert rec == {"k_sap_eo<3, 1, false>": {"SQ_INSTS_VALU": 10.0, "GRBM_GUI_ACTIVE": 7.0}}
     md = (tmp_path / "c.md").read_text()
     assert "| `k_sap_eo<3, 1, false>` | 7 | 10 |" in md
+
+
+def test_valu_record(tmp_path, monkeypatch):
+    """VALU occupancy: 4 cycles per wave64 instruction over SIMDs and per-XCD cycles, for the
+    launches with MR steps (the last 20), those without (the 20 before that differ) and
+    their difference; dropped once the kernel sources change."""
+    src = tmp_path / "paper_1109_4279_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "k.hip").write_text("kernel source\n")
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    k = "void wc::k_sap_eo<3, 1, false>(wc::SapLaunch)"
+    rows = []
+    # 22 launches without MR steps: 100 instructions, 800 GRBM cycles (100 per XCD);
+    # then 22 with: 300 instructions, 1600 cycles (200 per XCD)
+    for i in range(44):
+        v, g = (100.0, 800.0) if i < 22 else (300.0, 1600.0)
+        rows += [(i, k, "SQ_INSTS_VALU", v), (i, k, "GRBM_GUI_ACTIVE", g)]
+    with open(tmp_path / "q.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for i, kk, c, v in rows:
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": kk, "Counter_Name": c, "Counter_Value": v})
+    out = tmp_path / "profiles" / "valu_24c48.json"
+    bench.valu_record(str(tmp_path / "q.csv"), str(out), simds=4, xcds=8)
+    r = bench.measured_valu("k_sap_eo<3, 1, false>", "valu_24c48.json")
+    assert r["valu_busy_launch"] == pytest.approx(300 * 4 / (4 * 200))
+    assert r["valu_busy_without_mr_steps"] == pytest.approx(100 * 4 / (4 * 100))
+    assert r["valu_busy_mr_steps"] == pytest.approx(200 * 4 / (4 * 100))
+    (src / "k.hip").write_text("changed\n")
+    assert bench.measured_valu("k_sap_eo<3, 1, false>", "valu_24c48.json") is None
