@@ -298,14 +298,39 @@ def single_solves(lat, srcs, p, torch):
     return t, max(iters)
 
 
+COPY_GBS = {}  # measured device-copy rate, the second denominator of the D_w fractions
+
+
+def copy_bandwidth(torch, dev, gib=1, reps=5):
+    """Read + write rate of a plain device copy of `gib` GiB (torch's copy kernel; median of
+    `reps` timed copies after one warm-up), in GB/s."""
+    n = gib * (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    del src, dst
+    ts.sort()
+    return 2 * gib * (1 << 30) / ts[len(ts) // 2] / 1e9
+
+
 def dirac_rates(lat, V, precs, nrhs=1, iters=50):
     out = {}
+    copy = COPY_GBS.get("GB/s")
     for prec in precs:
         ms = lat.bench_dirac(prec=prec, nrhs=nrhs, iters=iters)
         rec = {"ms": ms, "Gflop/s": DW_FLOPS * V * nrhs / (ms * 1e-3) / 1e9}
         if nrhs == 1:
             gbs = dw_bytes(prec) * V / (ms * 1e-3) / 1e9
             rec.update({"GB/s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS})
+            if copy:
+                rec["frac_copy"] = gbs / copy
         else:
             # the operator counted once per rhs tile of the kernel, and once for all nrhs
             tile = lat_tile(lat, prec)
@@ -377,6 +402,9 @@ def roofline_record(lat, V, prec, nrhs, block, label, tile=1):
 def extra_workloads(wc, torch, dev, storage, lat_c4, pts):
     import synth
     out = {}
+    # the plain device copy's rate: the second denominator of the D_w fractions
+    COPY_GBS["GB/s"] = copy_bandwidth(torch, dev)
+    out["device_copy_GBps"] = COPY_GBS["GB/s"]
     # D_w on every size, one rhs; and the 12 rhs of 24^3 x 48 in one launch
     out["dirac_24c48"] = dirac_rates(lat_c4, 663552, ("f64", "f32", "f16", "bf16"))
     out["dirac_24c48_12rhs"] = dirac_rates(lat_c4, 663552, ("f64", storage), nrhs=12, iters=10)
