@@ -301,23 +301,23 @@ def single_solves(lat, srcs, p, torch):
 COPY_GBS = {}  # measured device-copy rate, the second denominator of the D_w fractions
 
 
-def copy_bandwidth(torch, dev, gib=1, reps=5):
-    """Read + write rate of a plain device copy of `gib` GiB (torch's copy kernel; median of
-    `reps` timed copies after one warm-up), in GB/s."""
+def copy_bandwidth(torch, dev, gib=1, reps=10):
+    """Read + write rate of a plain device copy of `gib` GiB: torch's copy kernel, `reps`
+    copies back to back between two events on torch's stream (the one the copies run on),
+    after one warm-up; in GB/s."""
     n = gib * (1 << 30) // 8
     src = torch.ones(n, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
-    torch.cuda.synchronize()
-    ts = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(reps):
-        t0 = time.perf_counter()
         dst.copy_(src)
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
     del src, dst
-    ts.sort()
-    return 2 * gib * (1 << 30) / ts[len(ts) // 2] / 1e9
+    return 2 * gib * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def dirac_rates(lat, V, precs, nrhs=1, iters=50):
