@@ -114,15 +114,23 @@ class FGCRResult:
         self.history = history
 
 
-def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 10000, x0=None):
-    """Restarted flexible GCR (Sec. 4), all in FP64.
+def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 10000, x0=None,
+         drop: float = 0.0, basis=np.complex128):
+    """Restarted flexible GCR (Sec. 4), in FP64 arithmetic.
 
     Each iteration k: phi_k = M(r); chi_k = D phi_k; orthogonalise chi_k against chi_0..chi_{k-1}
     by modified Gram-Schmidt (a_lk = <chi_l, chi_k>), normalise (b_k = |chi_k|), c_k = <chi_k, r>,
     r -= c_k chi_k.  The cycle ends after nkv iterations or when the recursive |r| <= tol |b| / 2;
     then the upper-triangular system b_k alpha_k + sum_{l>k} a_kl alpha_l = c_k gives the update
     x += sum alpha_k phi_k, and r = b - D x is recomputed.  The solve stops when the recomputed
-    |r| / |b| <= tol, else the recursion restarts from that residual."""
+    |r| / |b| <= tol, else the recursion restarts from that residual.
+
+    Iterative refinement (Sec. 4: the recursion in single precision, the residual and the
+    solution in double precision at each restart), in the reading taken here: the normalised
+    chi_k is stored in `basis` (np.complex64 for single precision; each component rounded) and
+    the residual is updated with chi_k as stored, so that only the stored vectors carry the
+    single precision; with drop > 0 a cycle also ends once the recursive |r| <= drop times the
+    recomputed |r| it started from."""
     bnorm = norm(b)
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - apply_op(x) if x0 is not None else b.copy()
@@ -134,6 +142,7 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
             return FGCRResult(x, True, iters, restarts, history)
         if iters >= maxit:
             return FGCRResult(x, False, iters, restarts, history)
+        r_start = norm(r)
         phis, chis = [], []
         a = np.zeros((nkv, nkv), dtype=np.complex128)
         bk = np.zeros(nkv)
@@ -148,12 +157,14 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
             bk[k] = norm(chi)
             chi = chi / bk[k]
             ck[k] = dot(chi, r)
+            chi = chi.astype(basis).astype(np.complex128)
             r = r - ck[k] * chi
             phis.append(phi)
             chis.append(chi)
             k_done = k + 1
             iters += 1
-            if norm(r) <= 0.5 * tol * bnorm or iters >= maxit:
+            rn = norm(r)
+            if rn <= 0.5 * tol * bnorm or rn <= drop * r_start or iters >= maxit:
                 break
         alpha = np.zeros(k_done, dtype=np.complex128)
         for k in range(k_done - 1, -1, -1):
@@ -166,12 +177,14 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
         history.append(norm(r) / bnorm)
 
 
-def sap_fgcr(U, A, b, block, nmr=4, ncy=5, nkv=16, tol=1e-10, bc_t=1, maxit=10000, eo=False):
-    """FGCR with the SAP preconditioner, the solver of Sec. 4, all FP64."""
+def sap_fgcr(U, A, b, block, nmr=4, ncy=5, nkv=16, tol=1e-10, bc_t=1, maxit=10000, eo=False, drop=0.0,
+             basis=np.complex128):
+    """FGCR with the SAP preconditioner, the solver of Sec. 4, in FP64 arithmetic (with
+    `basis` and `drop` as in fgcr)."""
     return fgcr(
         lambda v: apply_D(U, A, v, bc_t),
         lambda v: sap(U, A, v, block, nmr, ncy, bc_t, eo),
-        b, tol=tol, nkv=nkv, maxit=maxit)
+        b, tol=tol, nkv=nkv, maxit=maxit, drop=drop, basis=basis)
 
 
 def harmonic_ritz(Hbar: np.ndarray):

@@ -197,3 +197,43 @@ def test_fgcr_restarts_and_maxit(small):
     assert dirac.norm(r) / dirac.norm(b) <= 1e-10
     capped = solvers.sap_fgcr(U, A, b, BLOCK, nmr=2, ncy=1, nkv=2, tol=1e-10, maxit=3)
     assert not capped.converged and capped.iters == 3
+
+
+def test_fgcr_single_precision_basis_floor(small):
+    """Iterative refinement (Sec. 4): a basis stored in single precision leaves the recursive
+    residual and the true one parted by about the float rounding of the stored vectors, so
+    one long cycle stops on a true residual near 1e-8 that an FP64 basis takes to 1e-14;
+    the FP64 restarts still take the solve to the target."""
+    U, A = small
+    b = synth.gaussian_spinor(DIMS, seed=16)
+    kw = dict(nmr=4, ncy=5, nkv=32, tol=1e-13)
+    r64 = solvers.sap_fgcr(U, A, b, BLOCK, **kw)
+    r32 = solvers.sap_fgcr(U, A, b, BLOCK, basis=np.complex64, **kw)
+    assert r64.restarts == 1 and r64.history[1] <= 1e-13
+    assert 1e-10 < r32.history[1] < 1e-6
+    assert r32.converged and r32.restarts >= 2
+    for res in (r64, r32):
+        r = b - dirac.apply_D(U, A, res.x)
+        assert dirac.norm(r) / dirac.norm(b) <= 1e-13
+
+
+@pytest.mark.parametrize("basis", [np.complex128, np.complex64])
+def test_fgcr_cycle_drop(small, basis):
+    """drop = 1e-5: every restart before the last cuts the true residual by the drop (the
+    recursive one by exactly that bound; an FP64 basis keeps the two equal to rounding, a
+    single-precision one to its float floor, far below 1e-5 of the cycle's start), and the
+    answer is the dense solve's within cond * tol."""
+    U, A = small
+    b = synth.gaussian_spinor(DIMS, seed=16)
+    drop = 1e-5
+    res = solvers.sap_fgcr(U, A, b, BLOCK, nmr=4, ncy=5, nkv=32, tol=1e-12, drop=drop, basis=basis)
+    assert res.converged and res.restarts >= 3
+    h = res.history
+    slack = 1.0 + 1e-6 if basis is np.complex128 else 1.1
+    for i in range(len(h) - 2):
+        assert h[i + 1] <= drop * slack * h[i]
+    r = b - dirac.apply_D(U, A, res.x)
+    assert dirac.norm(r) / dirac.norm(b) <= 1e-12
+    M = dense.assemble(U, A)
+    xd = sla.lu_solve(sla.lu_factor(M), b.ravel()).reshape(b.shape)
+    assert dirac.norm(res.x - xd) / dirac.norm(xd) < np.linalg.cond(M) * 1e-12
