@@ -81,6 +81,16 @@ typedef struct {
                     WC_ERR_NOT_CONVERGED (x and stats written); 0 switches the test off */
   int timing;    /* 1: run the FGCR restart cycles eagerly with HIP events between the
                     phases and report t_sap/t_dirac/t_blas (slower; FGCR only) */
+  int basis_prec; /* storage of the FGCR Krylov basis chi_l: WC_F64, or WC_F32 for the
+                    single-precision recursion of Sec. 4 (iterative refinement: Gram-Schmidt
+                    against F32-stored vectors in FP64 arithmetic between restarts, the
+                    residual, the solution and the true residual at every restart in FP64).
+                    FGMRES-DR: WC_F64 only.  Errors: WC_ERR_ARG */
+  double drop;   /* a restart cycle also ends once its recursive residual is `drop` times
+                    the FP64 true residual it started from; 0: none with an FP64 basis,
+                    1e-6 with an F32 one (the stored basis bounds how far the recursion
+                    can follow the true residual within one cycle); else in (0, 1).
+                    FGMRES-DR: 0 only.  Errors: WC_ERR_ARG */
 } wc_solver_params;
 
 #define WC_HIST_MAX 64 /* restarts whose true residual wc_solver_stats keeps */
@@ -107,7 +117,7 @@ typedef struct {
 
 /* Fill p with the library defaults: nkv 16, ncy 5, nmr 4, sap_prec WC_F32, tol 1e-10,
  * maxit 10000, no initial guess, graphs on, automatic RHS tiles, MR block solver, D x = b,
- * stagnation test over 3 restarts, no phase timing. */
+ * stagnation test over 3 restarts, no phase timing, FP64 basis, drop 0. */
 void wc_default_params(wc_solver_params* p);
 
 /* Per-context kernel choices (a batched call uses those of its first context).
@@ -276,7 +286,7 @@ void wc_destroy(wc_ctx* ctx);
 /* Message of the last error on this thread (static storage, valid until the next call). */
 const char* wc_last_error(void);
 
-/* Interface version: 100 * major + minor (2.0). */
+/* Interface version: 100 * major + minor (2.1). */
 int wc_version(void);
 
 #ifdef __cplusplus

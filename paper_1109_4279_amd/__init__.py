@@ -48,7 +48,7 @@ def _set_fields(p, kw):
     for k, v in kw.items():
         if k not in names:
             raise TypeError(f"unknown solver parameter {k!r} (fields: {', '.join(sorted(names))})")
-        if k == "sap_prec" and isinstance(v, str):
+        if k in ("sap_prec", "basis_prec") and isinstance(v, str):
             v = PREC[v]
         setattr(p, k, v)
 
@@ -70,7 +70,7 @@ def _params(params, kw):
 
 def default_params(**kw) -> SolverParams:
     """The library's defaults (wc_default_params) with the fields named in kw replaced;
-    sap_prec may be given by name ("f64", "f32", "f16", "bf16")."""
+    sap_prec and basis_prec may be given by name ("f64", "f32", "f16", "bf16")."""
     p = SolverParams()
     _lib.load().wc_default_params(ctypes.byref(p))
     _set_fields(p, kw)

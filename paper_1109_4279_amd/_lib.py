@@ -22,6 +22,7 @@ class SolverParams(ctypes.Structure):
         ("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("x0_given", ctypes.c_int),
         ("use_graph", ctypes.c_int), ("nr_dirac", ctypes.c_int), ("nr_sap", ctypes.c_int),
         ("eo", ctypes.c_int), ("dagger", ctypes.c_int), ("stag", ctypes.c_int), ("timing", ctypes.c_int),
+        ("basis_prec", ctypes.c_int), ("drop", ctypes.c_double),
     ]
 
 

@@ -291,6 +291,7 @@ struct Batch {
   int pw = 4 * NKV_MAX;  // partial-sum width (at most RWG: sum_partials)
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
+  Field w;  // FGCR with an F32 basis: the FP64 direction D phi_k before its Gram-Schmidt
   DevBuf d_chi, d_phi;
   // FGCR directions in the preconditioner's storage, and their pointer tables
   Field dir[NKV_MAX];
@@ -663,7 +664,9 @@ static void unpack_batch(Batch& B, int prec, const Field& f, void* const* canon,
 
 struct SolveSetup {
   int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit, eo, stag, timing;
+  int basis_prec;  // FGCR Krylov basis storage: P_F64 or P_F32
   double tol;
+  double drop2;    // squared per-cycle drop of the recursive residual (0: none)
 };
 
 // Events recorded between the phases of an eagerly launched restart cycle (solver
@@ -733,11 +736,16 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.dir_sc = B.d_dir_sc.as<float* const>();
   a.dir_prec = s.sap_prec;
   a.fuse_sap = 0;
+  a.q = B.d_chi.as<void* const>();
+  a.w = nullptr;
+  a.drop2 = s.drop2;
   return a;
 }
 
-// fgcr: the directions live in the preconditioner's storage (dir); FGMRES-DR keeps its
-// preconditioned basis Z in FP64 (phi), which its deflated restarts recombine
+// fgcr: the directions live in the preconditioner's storage (dir) and the basis chi in
+// s.basis_prec (with an F32 basis the FP64 direction D phi_k gets a buffer of its own, w);
+// FGMRES-DR keeps its preconditioned basis Z in FP64 (phi), which its deflated restarts
+// recombine
 static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   const long long n = B.sites_rhs;
   B.x.ensure(P_F64, n);
@@ -746,8 +754,9 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   std::vector<double2*> pc(NKV_MAX, nullptr), pp(NKV_MAX, nullptr);
   std::vector<void*> pd(NKV_MAX, nullptr);
   std::vector<float*> pds(NKV_MAX, nullptr);
+  if (fgcr && s.basis_prec != P_F64) B.w.ensure(P_F64, n);
   for (int k = 0; k < s.nkv; ++k) {
-    B.chi[k].ensure(P_F64, n);
+    B.chi[k].ensure(fgcr ? s.basis_prec : P_F64, n);
     pc[k] = B.chi[k].d.as<double2>();
     if (fgcr) {
       B.dir[k].ensure(s.sap_prec, n);
@@ -788,8 +797,13 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
   const int gv = persistent_grid(va.nitems, 8);
   const int* skip = B.skip.as<int>();
   mark(tm, PH_BLAS, st);
+  const bool f64_basis = s.basis_prec == P_F64;
   for (int k = 0; k < s.nkv; ++k) {
     va.k = k;
+    // the FP64 direction D phi_k: chi_k itself with an FP64 basis, else the buffer w from
+    // which Gram-Schmidt writes the F32 chi_k
+    Field& wk = f64_basis ? B.chi[k] : B.w;
+    va.w = wk.d.as<double2>();
     // phi_k = M_SAP(r / |r_k|) as the preconditioner stores it (the input of step k > 0 was
     // written by step k - 1's residual update)
     if (k == 0) {
@@ -800,8 +814,8 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
     }
     run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
     mark(tm, PH_SAP, st);
-    // chi_k = D phi_k in FP64 arithmetic
-    run_dirac(B, P_F64, s.nr_d, B.dir[k], B.chi[k], nullptr, nullptr, skip, 0, 0, st);
+    // w = D phi_k in FP64 arithmetic
+    run_dirac(B, P_F64, s.nr_d, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
     mark(tm, PH_DIRAC, st);
     // classical Gram-Schmidt: all inner products, then the update of chi_k and r (and the
     // next preconditioner input); a system whose first pass cancelled takes a second pass
@@ -810,11 +824,11 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
     vu.sp = B.sap_rho.data();
     vu.sp_sc = B.sap_rho.scale();
     vu.fuse_sap = k + 1 < s.nkv;
-    launch_gs_dots(va, gv, st);
+    launch_gs_dots(s.basis_prec, va, gv, st);
     launch_reduce(RED_GS, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    launch_gs_update(s.sap_prec, vu, gv, st);
+    launch_gs_update(s.sap_prec, s.basis_prec, vu, gv, st);
     launch_reduce(RED_GS2, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
-    launch_gs_update2(s.sap_prec, vu, gv, st);
+    launch_gs_update2(s.sap_prec, s.basis_prec, vu, gv, st);
     launch_reduce(RED_RNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
     mark(tm, PH_BLAS, st);
   }
@@ -829,9 +843,9 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
 }
 
 static std::string setup_key(const SolveSetup& s) {
-  char buf[200];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d, s.nr_s,
-           s.maxit, s.eo, s.stag, s.tol);
+  char buf[240];
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%.17g/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d,
+           s.nr_s, s.maxit, s.eo, s.stag, s.tol, s.basis_prec, s.drop2);
   return buf;
 }
 
@@ -849,6 +863,7 @@ static std::string graph_key(const Batch& B, const SolveSetup& s) {
   add(B.x.data());
   add(B.b.data());
   add(B.r.data());
+  add(B.w.data());
   for (int i = 0; i < s.nkv; ++i) {
     add(B.chi[i].data());
     add(B.phi[i].data());
@@ -993,7 +1008,14 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   require(p.dagger == 0 || p.dagger == 1, WC_ERR_ARG, "dagger must be 0 or 1");
   require(p.stag >= 0, WC_ERR_ARG, "stag must be >= 0");
   require(p.timing == 0 || p.timing == 1, WC_ERR_ARG, "timing must be 0 or 1");
+  require(p.basis_prec == WC_F64 || p.basis_prec == WC_F32, WC_ERR_ARG, "basis_prec must be WC_F64 or WC_F32");
+  require(p.drop >= 0.0 && p.drop < 1.0, WC_ERR_ARG, "drop must be in [0, 1)");
   SolveSetup s;
+  s.basis_prec = p.basis_prec;
+  // drop 0: none with an FP64 basis; 1e-6 with an F32 one, whose stored vectors leave the
+  // recursive residual a few 1e-8 of the cycle's starting residual from the true one
+  const double drop = p.drop > 0.0 ? p.drop : (p.basis_prec == WC_F32 ? 1e-6 : 0.0);
+  s.drop2 = drop * drop;
   s.nkv = p.nkv;
   s.ncy = p.ncy;
   s.nmr = p.nmr;
@@ -1354,6 +1376,8 @@ void wc_default_params(wc_solver_params* p) {
   p->dagger = 0;
   p->stag = 3;
   p->timing = 0;
+  p->basis_prec = WC_F64;
+  p->drop = 0.0;
 }
 
 int wc_set_option(wc_ctx* c, int option, int value) {
@@ -1640,6 +1664,8 @@ static int solve_batch_impl(const std::vector<wc_ctx*>& ctxs, const std::vector<
     }
     SolveSetup s = make_setup(*p, ctxs[0], max_nrhs);
     require(kdefl < s.nkv, WC_ERR_ARG, "FGMRES-DR needs fewer deflated vectors than the cycle length");
+    require(kdefl < 0 || (p->basis_prec == WC_F64 && p->drop == 0.0), WC_ERR_ARG,
+            "FGMRES-DR keeps an FP64 basis: basis_prec must be WC_F64 and drop 0");
     if (kdefl >= 0)
       prepare_fgmres(*B, s);
     else
@@ -2013,7 +2039,7 @@ int wc_autotune_block(wc_ctx* c, const wc_solver_params* p, int block_out[4], vo
 
 const char* wc_last_error(void) { return g_last_error.c_str(); }
 
-int wc_version(void) { return 200; }
+int wc_version(void) { return 201; }
 
 void wc_destroy(wc_ctx* c) { delete c; }
 

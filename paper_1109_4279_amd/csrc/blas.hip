@@ -1,4 +1,5 @@
-// FP64 vector kernels of the restarted FGCR outer solver (arXiv:1109.4279, Sec. 4):
+// Vector kernels of the restarted FGCR outer solver (arXiv:1109.4279, Sec. 4), in FP64
+// arithmetic over an FP64 or F32-stored Krylov basis:
 // Gram-Schmidt against the previous directions, residual update, solution update,
 // and the conversions to and from the Schwarz preconditioner's precision.
 //
@@ -59,6 +60,9 @@ WC_D void store_sap_input(const VecLaunch& a, const VecSite& v, const Spinor<dou
 // it (the criterion of Daniel, Gragg, Kaufman and Stewart, Math. Comp. 30 (1976) 772) the
 // reduction asks for a second classical pass instead (k_gs_update, RED_GS2, k_gs_update2).
 // Partial layout per chunk: [2k a][2k e][|chi_k|^2][2 <chi_k, r>].
+// Before its Gram-Schmidt chi_k is the FP64 direction w = D phi_k; the earlier chi_l are
+// read from the basis storage QP (F32 for the single-precision recursion of Sec. 4).
+template <int QP>
 __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (4 * NKV_MAX + 4)];
   const int k = a.k;
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys]) continue;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    Spinor<double> ck = ld64(a.chi[k], v);
+    Spinor<double> ck = ld64(a.w, v);
     Spinor<double> r = ld64(a.r, v);
     if (!v.valid) {
       zero(ck);
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
       if (lane == 0) lds[wid * (4 * NKV_MAX + 4) + j] = x;
     };
     for (int l = 0; l < k; ++l) {
-      Spinor<double> cl = ld64_nt(a.chi[l], v);
+      Spinor<double> cl = ldq_nt<QP>(a.q[l], v);
       double are = 0.0, aim = 0.0, ere = 0.0, eim = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -118,13 +122,15 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   }
 }
 
-// chi_k <- (chi_k - sum_l a_lk chi_l) / b_k;  r <- r - c_k chi_k;  partial |r|^2; with
-// fuse_sap also the next preconditioner input r / |r_k| (storage P).
+// chi_k <- (w - sum_l a_lk chi_l) / b_k, stored in QP;  r <- r - c_k chi_k with chi_k as
+// stored (so that r stays the residual of the stored basis: the FP64 recursion then only
+// carries the rounding of its own arithmetic);  partial |r|^2; with fuse_sap also the next
+// preconditioner input r / |r_k| (storage P).
 // A system flagged by the reduction for a second pass (S.reorth) instead stores
-// chi_k' = chi_k - sum_l a_lk chi_l and the partial sums of the second pass,
+// chi_k' = w - sum_l a_lk chi_l in w (FP64) and the partial sums of the second pass,
 //   a2_l = <chi_l, chi_k'> (l < k), |chi_k'|^2 and <chi_k', r>,
 // as [2k a2][|chi_k'|^2][2 <chi_k', r>]; r is left for k_gs_update2.
-template <int P>
+template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (2 * NKV_MAX + 4)];
   const int k = a.k;
@@ -132,11 +138,11 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys]) continue;
     const SysState& S = a.sys[v.sys];
-    Spinor<double> ck = ld64(a.chi[k], v);
+    Spinor<double> ck = ld64(a.w, v);
     for (int l = 0; l < k; ++l) {
       const double2 al = S.a[l * NKV_MAX + k];
       const cplx<double> m = {-al.x, -al.y};
-      Spinor<double> cl = ld64_nt(a.chi[l], v);
+      Spinor<double> cl = ldq_nt<QP>(a.q[l], v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
       const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
       constexpr int LD = 2 * NKV_MAX + 4;
       if (v.valid)
-        st64(a.chi[k], v, ck);
+        st64(a.w, v, ck);
       else
         zero(ck);
       Spinor<double> r = ld64(a.r, v);
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
         if (lane == 0) lds[wid * LD + j] = x;
       };
       for (int l = 0; l < k; ++l) {
-        const Spinor<double> cl = ld64_nt(a.chi[l], v);
+        const Spinor<double> cl = ldq_nt<QP>(a.q[l], v);
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -199,12 +205,16 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
+        for (int c = 0; c < 3; ++c) ck.c[i][c] = ib * ck.c[i][c];
+      round_to<QP>(ck);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          ck.c[i][c] = ib * ck.c[i][c];
           cmac(r.c[i][c], mc, ck.c[i][c]);
           vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
         }
-      st64(a.chi[k], v, ck);
+      stq<QP>(a.q[k], v, ck);
       st64(a.r, v, r);
       if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
@@ -213,9 +223,10 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
   }
 }
 
-// Second Gram-Schmidt pass of the flagged systems: chi_k <- (chi_k' - sum_l a2_l chi_l) / b_k;
-// r <- r - c_k chi_k; partial |r|^2.  Other systems were finished by k_gs_update.
-template <int P>
+// Second Gram-Schmidt pass of the flagged systems: chi_k <- (chi_k' - sum_l a2_l chi_l) / b_k
+// (chi_k' from w), stored in QP; r <- r - c_k chi_k as stored; partial |r|^2.  Other
+// systems were finished by k_gs_update.
+template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
   __shared__ double lds[(WG / 64)];
   const int k = a.k;
@@ -224,10 +235,10 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
     if (a.skip[v.sys]) continue;
     const SysState& S = a.sys[v.sys];
     if (!S.reorth) continue;
-    Spinor<double> ck = ld64(a.chi[k], v);
+    Spinor<double> ck = ld64(a.w, v);
     for (int l = 0; l < k; ++l) {
       const cplx<double> m = {-S.a2[l].x, -S.a2[l].y};
-      Spinor<double> cl = ld64_nt(a.chi[l], v);
+      Spinor<double> cl = ldq_nt<QP>(a.q[l], v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -241,12 +252,16 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
+        for (int c = 0; c < 3; ++c) ck.c[i][c] = ib * ck.c[i][c];
+      round_to<QP>(ck);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          ck.c[i][c] = ib * ck.c[i][c];
           cmac(r.c[i][c], mc, ck.c[i][c]);
           vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
         }
-      st64(a.chi[k], v, ck);
+      stq<QP>(a.q[k], v, ck);
       st64(a.r, v, r);
       if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       S.rnorm2 = sum[0];
       S.k_done = k + 1;
       S.iters += 1;
-      if (!(sum[0] > S.thr2) || S.iters >= a.maxit) {
+      if (!(sum[0] > S.thr2) || !(sum[0] > S.cyc2) || S.iters >= a.maxit) {
         S.cycle_done = 1;
         a.skip[sys] = 1;
       }
@@ -435,6 +450,7 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       S.rnorm2 = sum[0];
       S.tol2 = a.tol * a.tol * sum[0];
       S.thr2 = 0.25 * S.tol2;
+      S.cyc2 = a.drop2 * sum[0];
       S.cycle_done = 0;
       S.converged = (sum[0] == 0.0);
       S.k_done = 0;
@@ -451,6 +467,7 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       break;
     case RED_INITR:  // residual of a given initial guess
       S.rnorm2 = sum[0];
+      S.cyc2 = a.drop2 * sum[0];
       S.prev_true2 = sum[0];
       if (!isfinite(sum[0])) S.breakdown = 1;
       S.converged = (sum[0] <= S.tol2) || S.breakdown;
@@ -459,6 +476,7 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       break;
     case RED_TRUE: {
       S.rnorm2 = sum[0];
+      S.cyc2 = a.drop2 * sum[0];
       S.restarts += 1;
       if (!isfinite(sum[0])) S.breakdown = 1;
       if (a.hist && S.restarts <= a.hist_max)
@@ -509,22 +527,39 @@ void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
     default: launch_vec(k_to_sap<P_BF16>, a, grid, st); break;
   }
 }
-void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_gs_dots, a, grid, st); }
-void launch_gs_update(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
+void launch_gs_dots(int basis_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  if (basis_prec == P_F32)
+    launch_vec(k_gs_dots<P_F32>, a, grid, st);
+  else
+    launch_vec(k_gs_dots<P_F64>, a, grid, st);
+}
+template <int QP> static void gs_update_q(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
   switch (sap_prec) {
-    case P_F64: launch_vec(k_gs_update<P_F64>, a, grid, st); break;
-    case P_F32: launch_vec(k_gs_update<P_F32>, a, grid, st); break;
-    case P_F16: launch_vec(k_gs_update<P_F16>, a, grid, st); break;
-    default: launch_vec(k_gs_update<P_BF16>, a, grid, st); break;
+    case P_F64: launch_vec(k_gs_update<P_F64, QP>, a, grid, st); break;
+    case P_F32: launch_vec(k_gs_update<P_F32, QP>, a, grid, st); break;
+    case P_F16: launch_vec(k_gs_update<P_F16, QP>, a, grid, st); break;
+    default: launch_vec(k_gs_update<P_BF16, QP>, a, grid, st); break;
   }
 }
-void launch_gs_update2(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
+template <int QP> static void gs_update2_q(int sap_prec, const VecLaunch& a, int grid, hipStream_t st) {
   switch (sap_prec) {
-    case P_F64: launch_vec(k_gs_update2<P_F64>, a, grid, st); break;
-    case P_F32: launch_vec(k_gs_update2<P_F32>, a, grid, st); break;
-    case P_F16: launch_vec(k_gs_update2<P_F16>, a, grid, st); break;
-    default: launch_vec(k_gs_update2<P_BF16>, a, grid, st); break;
+    case P_F64: launch_vec(k_gs_update2<P_F64, QP>, a, grid, st); break;
+    case P_F32: launch_vec(k_gs_update2<P_F32, QP>, a, grid, st); break;
+    case P_F16: launch_vec(k_gs_update2<P_F16, QP>, a, grid, st); break;
+    default: launch_vec(k_gs_update2<P_BF16, QP>, a, grid, st); break;
   }
+}
+void launch_gs_update(int sap_prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  if (basis_prec == P_F32)
+    gs_update_q<P_F32>(sap_prec, a, grid, st);
+  else
+    gs_update_q<P_F64>(sap_prec, a, grid, st);
+}
+void launch_gs_update2(int sap_prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  if (basis_prec == P_F32)
+    gs_update2_q<P_F32>(sap_prec, a, grid, st);
+  else
+    gs_update2_q<P_F64>(sap_prec, a, grid, st);
 }
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st) { launch_vec(k_x_update, a, grid, st); }
 void launch_x_update_dir(const VecLaunch& a, int grid, hipStream_t st) {

@@ -93,6 +93,7 @@ struct SysState {
   double bnorm2;
   double rnorm2;       // |r|^2, recursive inside a cycle, true after a restart
   double thr2;         // cycle stops once rnorm2 <= thr2
+  double cyc2;         // ... or once rnorm2 <= cyc2 (drop^2 x the true |r|^2 the cycle started from)
   double tol2;         // solve stops once the true |r|^2 <= tol2
   int cycle_done;
   int converged;
@@ -164,17 +165,24 @@ struct VecLaunch {
   float* const* dir_sc;
   int dir_prec;
   int fuse_sap;
+  // FGCR Krylov basis chi_l (device array of NKV_MAX pointers, storage F64 or F32) and the
+  // current direction D phi_k in FP64 before its Gram-Schmidt (with an FP64 basis, chi_k
+  // itself: the update then overwrites it in place)
+  void* const* q;
+  double2* w;
+  double drop2;            // a cycle ends once |r|^2 <= drop2 x its starting true |r|^2 (0: never)
 };
 // eta(P) = r / |r|, the preconditioner's input at the start of a restart cycle (later
 // steps get theirs from the residual update); the FGCR direction phi_k is the
 // preconditioner's output as stored (GCR is invariant to the scale of a direction)
 void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
-void launch_gs_dots(const VecLaunch& a, int grid, hipStream_t st);     // <chi_l, chi_k>, <chi_l, r>, |chi_k|^2, <chi_k, r>
-// chi_k = (chi_k - sum a_lk chi_l)/b_k; r -= c_k chi_k; |r|^2.  A system whose first pass
-// cancelled (reorth) instead keeps chi_k - sum a_lk chi_l and its second-pass dots, and
-// launch_gs_update2 finishes it after the RED_GS2 reduction.
-void launch_gs_update(int sap_prec, const VecLaunch& a, int grid, hipStream_t st);
-void launch_gs_update2(int sap_prec, const VecLaunch& a, int grid, hipStream_t st);
+// Gram-Schmidt kernels for a basis stored in basis_prec (P_F64 or P_F32)
+void launch_gs_dots(int basis_prec, const VecLaunch& a, int grid, hipStream_t st);  // <chi_l, w>, <chi_l, r>, |w|^2, <w, r>
+// chi_k = (w - sum a_lk chi_l)/b_k in the basis storage; r -= c_k chi_k (chi_k as stored);
+// |r|^2.  A system whose first pass cancelled (reorth) instead keeps w - sum a_lk chi_l in w
+// and its second-pass dots, and launch_gs_update2 finishes it after the RED_GS2 reduction.
+void launch_gs_update(int sap_prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st);
+void launch_gs_update2(int sap_prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st);
 void launch_x_update(const VecLaunch& a, int grid, hipStream_t st);     // x += sum alpha_l phi_l (FP64 phi)
 void launch_x_update_dir(const VecLaunch& a, int grid, hipStream_t st); // x += sum alpha_l dir_l
 void launch_norm2(const VecLaunch& a, const double2* v, int grid, hipStream_t st);  // |v|^2 partials

@@ -51,6 +51,42 @@ WC_D void st64(double2* base, const VecSite& v, const Spinor<double>& p) {
   SpinorIO<P_F64>::store(FieldRef{(void*)(base + v.off * 12), nullptr, v.V}, v.s, p);
 }
 
+// FGCR Krylov basis vectors in their storage QP (F64, or F32 for the single-precision
+// recursion), read non-temporally and widened to FP64, or stored from FP64.
+template <int QP> WC_D Spinor<double> ldq_nt(const void* base, const VecSite& v);
+template <> WC_D Spinor<double> ldq_nt<P_F64>(const void* base, const VecSite& v) {
+  return ld64_nt((const double2*)base, v);
+}
+template <> WC_D Spinor<double> ldq_nt<P_F32>(const void* base, const VecSite& v) {
+  const gptr_t<gf4v> p = (gptr_t<gf4v>)((const float4*)base + v.off * 6);
+  Spinor<double> o;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const gf4v x = __builtin_nontemporal_load(p + (size_t)k * v.V + v.s);
+    o.c[(2 * k) / 3][(2 * k) % 3] = {double(x.x), double(x.y)};
+    o.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {double(x.z), double(x.w)};
+  }
+  return o;
+}
+template <int QP> WC_D void stq(void* base, const VecSite& v, const Spinor<double>& p);
+template <> WC_D void stq<P_F64>(void* base, const VecSite& v, const Spinor<double>& p) { st64((double2*)base, v, p); }
+template <> WC_D void stq<P_F32>(void* base, const VecSite& v, const Spinor<double>& p) {
+  Spinor<float> o;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.c[i][c] = {float(p.c[i][c].re), float(p.c[i][c].im)};
+  SpinorIO<P_F32>::store(FieldRef{(void*)((float4*)base + v.off * 6), nullptr, v.V}, v.s, o);
+}
+// p as stq<QP> stores it (F32: each component rounded to the nearest float)
+template <int QP> WC_D void round_to(Spinor<double>& p) {
+  if (QP == P_F64) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.c[i][c] = {double(float(p.c[i][c].re)), double(float(p.c[i][c].im))};
+}
+
 // reduce NV values of the work-group and store them as this chunk's partial
 template <int NV> WC_D void put_partial(const VecLaunch& a, const VecSite& v, double* vals, double* lds) {
   block_sum<NV>(vals, lds);

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     # the Python binding declares exactly the header's entry points
     assert sorted(_lib.exported_symbols()) == _declared()
     lib2 = _lib.load()
-    assert lib2.wc_version() == 200
+    assert lib2.wc_version() == 201
 
 
 def _param_counts():
@@ -190,4 +190,4 @@ int main(void) {{
     assert cc.returncode == 0, cc.stderr
     run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert run.returncode == 0, (run.returncode, run.stderr)
-    assert run.stdout.strip() == "200"
+    assert run.stdout.strip() == "201"

@@ -91,7 +91,53 @@ def test_fgcr_multi_rhs_point_sources():
     assert rel(x[5], to_np(one)) < 1e-8
 
 
-def test_fgcr_uneven_batch():
+@pytest.mark.parametrize("basis,drop", [("f64", 1e-5), ("f32", 0.0), ("f32", 1e-3)])
+def test_fgcr_iterative_refinement_matches_oracle(basis, drop):
+    """Iterative refinement (Sec. 4) on 4^4 with FP64 SAP: a cycle also ends once its
+    recursive residual has dropped by `drop` below the true residual it started from (0 with
+    an F32 basis means 1e-6); an F32 basis is stored rounded and the residual is updated
+    with the stored vectors.  Iterations within one and restarts equal to the oracle's run
+    of the same reading, the true residual after every restart following the oracle's, and
+    the answer the dense solve's within cond * tol."""
+    dims, block, m0, csw = (4, 4, 4, 4), (2, 2, 2, 2), 0.0, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims)
+    x, st = lat.solve(to_dev(b), nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec="f64", basis_prec=basis, drop=drop)
+    s = st[0]
+    A = clover(dims, m0, csw)
+    ref = solvers.sap_fgcr(gauge(dims), A, b, block, nmr=4, ncy=5, nkv=16, tol=1e-10, drop=drop or 1e-6,
+                           basis=np.complex64 if basis == "f32" else np.complex128)
+    assert s["status"] == 0 and ref.converged and ref.restarts >= 2
+    assert abs(s["iters"] - ref.iters) <= 1
+    assert s["restarts"] == ref.restarts
+    for got, want in zip(s["res_hist"][:-1], ref.history[1:-1]):
+        assert got == pytest.approx(want, rel=0.2)
+    x = to_np(x)
+    assert _true_res(dims, m0, csw, x, b) <= 1e-10
+    M = dense.assemble(gauge(dims), A)
+    xd = sla.lu_solve(sla.lu_factor(M), b.ravel()).reshape(b.shape)
+    assert rel(x, xd) < np.linalg.cond(M) * 1e-10
+
+
+def test_fgcr_f32_basis_16c32_mixed():
+    """16^3 x 32, BF16 SAP storage with the even/odd block solver: the F32 basis (the
+    single-precision recursion between FP64 restarts) reaches 1e-10 by the oracle's D within
+    three iterations of the FP64 basis, and the two answers agree to 1e-8."""
+    dims, block, m0, csw = (32, 16, 16, 16), (4, 4, 4, 4), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims)
+    kw = dict(sap_prec="bf16", eo=1, nkv=16, ncy=5, nmr=4, tol=1e-10)
+    x64, s64 = lat.solve(to_dev(b), **kw)
+    x32, s32 = lat.solve(to_dev(b), basis_prec="f32", **kw)
+    assert s64[0]["status"] == 0 and s32[0]["status"] == 0
+    assert s32[0]["restarts"] >= 2
+    assert s32[0]["iters"] <= s64[0]["iters"] + 3
+    assert _true_res(dims, m0, csw, to_np(x32), b) <= 1e-10
+    assert rel(to_np(x32), to_np(x64)) < 1e-8
+
+
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_fgcr_uneven_batch(basis):
     import paper_1109_4279_amd as wc
     m0, csw = -0.1, 1.0
     specs = [((16, 8, 8, 8), (4, 4, 4, 4)), ((24, 12, 12, 12), (4, 3, 3, 3)), ((8, 4, 4, 4), (2, 2, 2, 2))]
@@ -99,7 +145,7 @@ def test_fgcr_uneven_batch():
     for i, (dims, block) in enumerate(specs):
         lats.append(lattice(dims, block, m0, csw, seed=synth.GAUGE_SEED + i))
         bs.append(synth.gaussian_spinor(dims, nrhs=4, seed=synth.RHS_SEED + i))
-    xs, st = wc.solve_batch(lats, [to_dev(b) for b in bs], tol=1e-10, sap_prec="f32")
+    xs, st = wc.solve_batch(lats, [to_dev(b) for b in bs], tol=1e-10, sap_prec="f32", basis_prec=basis)
     k = 0
     for i, (dims, block) in enumerate(specs):
         U = synth.gauge_field(dims, seed=synth.GAUGE_SEED + i)
@@ -152,13 +198,18 @@ def test_uneven_batch_kept_between_calls_and_dropped_with_its_lattices():
     check(wc.solve_batch(lats, [to_dev(b) for b in b2], **kw)[0], b2)
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_graph_replay_equals_eager(basis):
+    """Bitwise the same answer from the captured cycle, the eager one and a replay; the basis
+    precision is part of the graph's key (an F64-basis call after an F32 one re-captures)."""
     dims, block = (8, 4, 4, 4), (2, 2, 2, 2)
     lat = lattice(dims, block)
     b = to_dev(synth.gaussian_spinor(dims, nrhs=2, seed=43))
-    xg, sg = lat.solve(b, tol=1e-10, use_graph=1)
-    xe, se = lat.solve(b, tol=1e-10, use_graph=0)
-    xg2, _ = lat.solve(b, tol=1e-10, use_graph=1)
+    other = "f64" if basis == "f32" else "f32"
+    lat.solve(b, tol=1e-10, use_graph=1, basis_prec=other)
+    xg, sg = lat.solve(b, tol=1e-10, use_graph=1, basis_prec=basis)
+    xe, se = lat.solve(b, tol=1e-10, use_graph=0, basis_prec=basis)
+    xg2, _ = lat.solve(b, tol=1e-10, use_graph=1, basis_prec=basis)
     assert np.array_equal(to_np(xg), to_np(xe))
     assert np.array_equal(to_np(xg), to_np(xg2))
     assert [s["iters"] for s in sg] == [s["iters"] for s in se]
@@ -248,11 +299,17 @@ def test_solver_parameter_errors():
     lat = lattice(dims, block)
     b = to_dev(synth.gaussian_spinor(dims, seed=46))
     bad = [dict(nkv=0), dict(nkv=33), dict(ncy=0), dict(nmr=0), dict(sap_prec=4), dict(sap_prec=-1),
-           dict(tol=0.0), dict(tol=float("nan")), dict(maxit=0), dict(eo=2), dict(dagger=2)]
+           dict(tol=0.0), dict(tol=float("nan")), dict(maxit=0), dict(eo=2), dict(dagger=2),
+           dict(basis_prec=2), dict(basis_prec=-1), dict(drop=-1e-5), dict(drop=1.0), dict(drop=float("nan"))]
     for kw in bad:
         for solve in (lat.solve, lambda rhs, **k: lat.solve_fgmres_dr(rhs, k=0, **k)):
             with pytest.raises(wc.WCError) as e:
                 solve(b, **kw)
             assert e.value.code == -1, kw
+    # FGMRES-DR keeps an FP64 basis
+    for kw in (dict(basis_prec="f32"), dict(drop=1e-5)):
+        with pytest.raises(wc.WCError) as e:
+            lat.solve_fgmres_dr(b, k=0, **kw)
+        assert e.value.code == -1, kw
     x, st = lat.solve(b, tol=1e-10)
     assert st[0]["status"] == 0 and _true_res(dims, -0.1, 1.0, to_np(x), to_np(b)) <= 1e-10

@@ -49,6 +49,24 @@ def test_fgcr_near_critical_matches_oracle_iterations(eo):
     assert dirac.norm(b - dirac.apply_D(U, A, to_np(x))) / dirac.norm(b) <= 1e-10
 
 
+def test_fgcr_near_critical_f32_basis():
+    """The same 8^4 system with the F32 basis: cycles of 16 directions whose first
+    Gram-Schmidt pass cancels against F32-stored vectors still take their second pass, and
+    the solve reaches 1e-10 by the oracle's D within two iterations of the oracle's FP64
+    count."""
+    dims, block, m0, csw = (8, 8, 8, 8), (4, 4, 4, 4), -0.17, 1.0
+    iters, _restarts, _hist = _golden()[0]
+    lat = lattice(dims, block, m0, csw)
+    b = synth.gaussian_spinor(dims)
+    x, st = lat.solve(to_dev(b), sap_prec="f64", eo=0, nkv=16, ncy=5, nmr=4, tol=1e-10, basis_prec="f32")
+    s = st[0]
+    assert s["status"] == 0
+    assert s["reorth"] > 0
+    assert abs(s["iters"] - iters) <= 2
+    U, A = gauge(dims), clover(dims, m0, csw)
+    assert dirac.norm(b - dirac.apply_D(U, A, to_np(x))) / dirac.norm(b) <= 1e-10
+
+
 def test_stagnation_stops_the_solve():
     """A tolerance below FP64 rounding: the true residual stops dropping, and after `stag`
     restarts without a drop the solve returns WC_ERR_NOT_CONVERGED with x and the stats
