@@ -126,10 +126,11 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
     |r| / |b| <= tol, else the recursion restarts from that residual.
 
     Iterative refinement (Sec. 4: the recursion in single precision, the residual and the
-    solution in double precision at each restart), in the reading taken here: the normalised
-    chi_k is stored in `basis` (np.complex64 for single precision; each component rounded) and
-    the residual is updated with chi_k as stored, so that only the stored vectors carry the
-    single precision; with drop > 0 a cycle also ends once the recursive |r| <= drop times the
+    solution in double precision at each restart), in the reading taken here: D phi_k and the
+    normalised chi_k are held in `basis` (np.complex64 for single precision: the product
+    rounded, each component) and the residual is updated with chi_k as held, so that D phi_k
+    and the stored vectors carry the single precision and the Gram-Schmidt arithmetic stays
+    double; with drop > 0 a cycle also ends once the recursive |r| <= drop times the
     recomputed |r| it started from."""
     bnorm = norm(b)
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -150,7 +151,7 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
         k_done = 0
         for k in range(nkv):
             phi = precond(r)
-            chi = apply_op(phi)
+            chi = apply_op(phi).astype(basis).astype(np.complex128)
             for l in range(k):
                 a[l, k] = dot(chis[l], chi)
                 chi = chi - a[l, k] * chis[l]
