@@ -82,10 +82,11 @@ typedef struct {
   int timing;    /* 1: run the FGCR restart cycles eagerly with HIP events between the
                     phases and report t_sap/t_dirac/t_blas (slower; FGCR only) */
   int basis_prec; /* storage of the FGCR Krylov basis chi_l: WC_F64, or WC_F32 for the
-                    single-precision recursion of Sec. 4 (iterative refinement: Gram-Schmidt
-                    against F32-stored vectors in FP64 arithmetic between restarts, the
-                    residual, the solution and the true residual at every restart in FP64).
-                    FGMRES-DR: WC_F64 only.  Errors: WC_ERR_ARG */
+                    single-precision recursion of Sec. 4 (iterative refinement: D phi_k in
+                    FP32 arithmetic, Gram-Schmidt against the F32-stored vectors in FP64
+                    arithmetic between restarts; the residual, the solution and the true
+                    residual at every restart in FP64).  FGMRES-DR: WC_F64 only.
+                    Errors: WC_ERR_ARG */
   double drop;   /* a restart cycle also ends once its recursive residual is `drop` times
                     the FP64 true residual it started from; 0: none with an FP64 basis,
                     1e-6 with an F32 one (the stored basis bounds how far the recursion
@@ -264,9 +265,10 @@ int wc_force(wc_ctx* ctx, void* F, const void* phi, const wc_solver_params* p, w
              void* X, void* stream);
 
 /* Autotune for solves of nrhs right-hand sides whose preconditioner runs in prec: time the
- * RHS tile of D in prec, of the FP64 D of the outer solver and of both block solvers in
- * prec, and keep the fastest in the context.  nr_out[0..3] receive the chosen tiles:
- * D in prec, FP64 D, plain block solver, even/odd block solver. */
+ * RHS tile of D in prec, of the outer solver's FP64 D (and, for 16-bit prec, its FP32 D of
+ * an F32 basis) and of both block solvers in prec, and keep the fastest in the context.
+ * nr_out[0..3] receive the chosen tiles: D in prec, FP64 D, plain block solver, even/odd
+ * block solver. */
 int wc_autotune(wc_ctx* ctx, int nrhs, int prec, int nr_out[4], void* stream);
 
 /* Choose the Schwarz block shape of the context among the valid shapes with at most 256

@@ -291,7 +291,7 @@ struct Batch {
   int pw = 4 * NKV_MAX;  // partial-sum width (at most RWG: sum_partials)
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
-  Field w;  // FGCR with an F32 basis: the FP64 direction D phi_k before its Gram-Schmidt
+  Field w;  // FGCR with an F32 basis: the direction D phi_k (F32) before its Gram-Schmidt
   DevBuf d_chi, d_phi;
   // FGCR directions in the preconditioner's storage, and their pointer tables
   Field dir[NKV_MAX];
@@ -664,7 +664,8 @@ static void unpack_batch(Batch& B, int prec, const Field& f, void* const* canon,
 
 struct SolveSetup {
   int nkv, ncy, nmr, sap_prec, nr_d, nr_s, maxit, eo, stag, timing;
-  int basis_prec;  // FGCR Krylov basis storage: P_F64 or P_F32
+  int basis_prec;  // FGCR Krylov basis storage: P_F64 or P_F32 (then D phi_k in FP32 arithmetic)
+  int nr_d32;      // rhs per lane of that FP32 D
   double tol;
   double drop2;    // squared per-cycle drop of the recursive residual (0: none)
 };
@@ -743,7 +744,7 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
 }
 
 // fgcr: the directions live in the preconditioner's storage (dir) and the basis chi in
-// s.basis_prec (with an F32 basis the FP64 direction D phi_k gets a buffer of its own, w);
+// s.basis_prec (with an F32 basis, D phi_k is formed in FP32 into a buffer of its own, w);
 // FGMRES-DR keeps its preconditioned basis Z in FP64 (phi), which its deflated restarts
 // recombine
 static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
@@ -754,7 +755,7 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   std::vector<double2*> pc(NKV_MAX, nullptr), pp(NKV_MAX, nullptr);
   std::vector<void*> pd(NKV_MAX, nullptr);
   std::vector<float*> pds(NKV_MAX, nullptr);
-  if (fgcr && s.basis_prec != P_F64) B.w.ensure(P_F64, n);
+  if (fgcr && s.basis_prec != P_F64) B.w.ensure(P_F32, n);
   for (int k = 0; k < s.nkv; ++k) {
     B.chi[k].ensure(fgcr ? s.basis_prec : P_F64, n);
     pc[k] = B.chi[k].d.as<double2>();
@@ -784,7 +785,8 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   // everything a captured cycle touches must exist before capture starts
   B.lats(P_F64, nullptr);
   B.lats(s.sap_prec, nullptr, s.eo != 0);
-  for (int nr : {1, s.nr_d})
+  if (fgcr && s.basis_prec != P_F64) B.lats(P_F32, nullptr);
+  for (int nr : {1, s.nr_d, s.nr_d32})
     for (int sel = 0; sel < 3; ++sel) B.items_dirac(nr, sel);
   for (int bv : B.bvols())
     for (int c = 0; c < 2; ++c) B.items_sap(c, s.nr_s, bv);
@@ -800,10 +802,10 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
   const bool f64_basis = s.basis_prec == P_F64;
   for (int k = 0; k < s.nkv; ++k) {
     va.k = k;
-    // the FP64 direction D phi_k: chi_k itself with an FP64 basis, else the buffer w from
+    // the direction D phi_k: chi_k itself with an FP64 basis, else the F32 buffer w from
     // which Gram-Schmidt writes the F32 chi_k
     Field& wk = f64_basis ? B.chi[k] : B.w;
-    va.w = wk.d.as<double2>();
+    va.w = wk.data();
     // phi_k = M_SAP(r / |r_k|) as the preconditioner stores it (the input of step k > 0 was
     // written by step k - 1's residual update)
     if (k == 0) {
@@ -814,8 +816,12 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
     }
     run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
     mark(tm, PH_SAP, st);
-    // w = D phi_k in FP64 arithmetic
-    run_dirac(B, P_F64, s.nr_d, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
+    // w = D phi_k: FP64 arithmetic with an FP64 basis, FP32 (the single-precision
+    // recursion) with an F32 one
+    if (f64_basis)
+      run_dirac(B, P_F64, s.nr_d, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
+    else
+      run_dirac(B, P_F32, s.nr_d32, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
     mark(tm, PH_DIRAC, st);
     // classical Gram-Schmidt: all inner products, then the update of chi_k and r (and the
     // next preconditioner input); a system whose first pass cancelled takes a second pass
@@ -844,8 +850,8 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
 
 static std::string setup_key(const SolveSetup& s) {
   char buf[240];
-  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%.17g/%d/%.17g", s.nkv, s.ncy, s.nmr, s.sap_prec, s.nr_d,
-           s.nr_s, s.maxit, s.eo, s.stag, s.tol, s.basis_prec, s.drop2);
+  snprintf(buf, sizeof buf, "%d/%d/%d/%d/%d/%d/%d/%d/%d/%.17g/%d/%.17g/%d", s.nkv, s.ncy, s.nmr, s.sap_prec,
+           s.nr_d, s.nr_s, s.maxit, s.eo, s.stag, s.tol, s.basis_prec, s.drop2, s.nr_d32);
   return buf;
 }
 
@@ -877,7 +883,7 @@ static std::string graph_key(const Batch& B, const SolveSetup& s) {
     add(f->scale());
   }
   for (const DevBuf* d : {&B.sys, &B.skip, &B.partials, &B.hist, &B.d_chi, &B.d_phi, &B.d_arn_v, &B.arn,
-                          &B.sys_part, &B.sys_nchunks, &B.d_lats[P_F64], &B.d_lats[s.sap_prec]})
+                          &B.sys_part, &B.sys_nchunks, &B.d_lats[P_F64], &B.d_lats[s.sap_prec], &B.d_lats[P_F32]})
     add(d->p);
   add(B.arn_vlast.data());
   for (const auto& kv : B.dirac_items) add(kv.second.d.p);
@@ -1026,6 +1032,7 @@ static SolveSetup make_setup(const wc_solver_params& p, wc_ctx* c, int max_nrhs)
   s.stag = p.stag;
   s.timing = p.timing;
   s.nr_d = pick_nr(c, max_nrhs, P_F64, false, p.nr_dirac);
+  s.nr_d32 = pick_nr(c, max_nrhs, P_F32, false, 0);
   s.nr_s = pick_nr(c, max_nrhs, p.sap_prec, true, p.nr_sap, s.eo);
   return s;
 }
@@ -1934,9 +1941,11 @@ int wc_autotune(wc_ctx* c, int nrhs, int prec, int nr_out[4], void* stream) {
     require(c && nrhs >= 1, WC_ERR_ARG, "bad argument");
     check_prec(prec);
     const int cands[4] = {1, 2, 3, 4};
-    // D tiles: in prec and, for the outer solver, in FP64
+    // D tiles: in prec and, for the outer solver, in FP64 and (16-bit prec) in FP32, the D
+    // of the recursion over an F32 basis
     std::vector<int> dps = {prec};
     if (prec != P_F64) dps.push_back(P_F64);
+    if (is16(prec)) dps.push_back(P_F32);
     for (int dp : dps) {
       double best = 1e30;
       int nd = 1;

@@ -60,7 +60,7 @@ WC_D void store_sap_input(const VecLaunch& a, const VecSite& v, const Spinor<dou
 // it (the criterion of Daniel, Gragg, Kaufman and Stewart, Math. Comp. 30 (1976) 772) the
 // reduction asks for a second classical pass instead (k_gs_update, RED_GS2, k_gs_update2).
 // Partial layout per chunk: [2k a][2k e][|chi_k|^2][2 <chi_k, r>].
-// Before its Gram-Schmidt chi_k is the FP64 direction w = D phi_k; the earlier chi_l are
+// Before its Gram-Schmidt chi_k is the direction w = D phi_k; w and the earlier chi_l are
 // read from the basis storage QP (F32 for the single-precision recursion of Sec. 4).
 template <int QP>
 __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys]) continue;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    Spinor<double> ck = ld64(a.w, v);
+    Spinor<double> ck = ldq<QP>(a.w, v);
     Spinor<double> r = ld64(a.r, v);
     if (!v.valid) {
       zero(ck);
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
 // carries the rounding of its own arithmetic);  partial |r|^2; with fuse_sap also the next
 // preconditioner input r / |r_k| (storage P).
 // A system flagged by the reduction for a second pass (S.reorth) instead stores
-// chi_k' = w - sum_l a_lk chi_l in w (FP64) and the partial sums of the second pass,
+// chi_k' = w - sum_l a_lk chi_l in w (storage QP) and the partial sums of the second pass,
 //   a2_l = <chi_l, chi_k'> (l < k), |chi_k'|^2 and <chi_k', r>,
 // as [2k a2][|chi_k'|^2][2 <chi_k', r>]; r is left for k_gs_update2.
 template <int P, int QP>
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys]) continue;
     const SysState& S = a.sys[v.sys];
-    Spinor<double> ck = ld64(a.w, v);
+    Spinor<double> ck = ldq<QP>(a.w, v);
     for (int l = 0; l < k; ++l) {
       const double2 al = S.a[l * NKV_MAX + k];
       const cplx<double> m = {-al.x, -al.y};
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
       const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
       constexpr int LD = 2 * NKV_MAX + 4;
       if (v.valid)
-        st64(a.w, v, ck);
+        stq<QP>(a.w, v, ck);
       else
         zero(ck);
       Spinor<double> r = ld64(a.r, v);
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
     if (a.skip[v.sys]) continue;
     const SysState& S = a.sys[v.sys];
     if (!S.reorth) continue;
-    Spinor<double> ck = ld64(a.w, v);
+    Spinor<double> ck = ldq<QP>(a.w, v);
     for (int l = 0; l < k; ++l) {
       const cplx<double> m = {-S.a2[l].x, -S.a2[l].y};
       Spinor<double> cl = ldq_nt<QP>(a.q[l], v);

@@ -34,8 +34,9 @@ template <class R, class T> WC_D Spinor<R> to_real(const Spinor<T>& p) {
 // STAGE: every work item is one 256-site tile (Schwarz blocks of 256 sites); the tile's
 // input spinors are decoded once into LDS and the in-tile neighbours are read from there,
 // so each spinor leaves HBM/L2 once per tile instead of once per neighbour.
-// PIN: storage precision of the input (FP64 arithmetic may read a reduced-precision input,
-// converted exactly to double; every other launch reads its own precision).
+// PIN: storage precision of the input (FP64 and FP32 arithmetic may read an input of
+// another storage, widened or rounded to the arithmetic's precision; the 16-bit launches
+// read their own precision).
 template <int P, int NR, bool STAGE, int PIN = P>
 __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
   typedef typename Real<P>::T R;
@@ -240,8 +241,16 @@ void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t 
     }
     return;
   }
+  if (prec == P_F32) {
+    switch (a.in_prec) {
+      case P_F64: launch_p<P_F32, P_F64>(a, nr, grid, st); break;
+      case P_F32: launch_p<P_F32, P_F32>(a, nr, grid, st); break;
+      case P_F16: launch_p<P_F32, P_F16>(a, nr, grid, st); break;
+      default: launch_p<P_F32, P_BF16>(a, nr, grid, st); break;
+    }
+    return;
+  }
   switch (prec) {
-    case P_F32: launch_p<P_F32, P_F32>(a, nr, grid, st); break;
     case P_F16: launch_p<P_F16, P_F16>(a, nr, grid, st); break;
     default: launch_p<P_BF16, P_BF16>(a, nr, grid, st); break;
   }

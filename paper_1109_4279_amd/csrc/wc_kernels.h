@@ -166,10 +166,10 @@ struct VecLaunch {
   int dir_prec;
   int fuse_sap;
   // FGCR Krylov basis chi_l (device array of NKV_MAX pointers, storage F64 or F32) and the
-  // current direction D phi_k in FP64 before its Gram-Schmidt (with an FP64 basis, chi_k
-  // itself: the update then overwrites it in place)
+  // current direction D phi_k before its Gram-Schmidt, in the basis storage (with an FP64
+  // basis, chi_k itself: the update then overwrites it in place)
   void* const* q;
-  double2* w;
+  void* w;
   double drop2;            // a cycle ends once |r|^2 <= drop2 x its starting true |r|^2 (0: never)
 };
 // eta(P) = r / |r|, the preconditioner's input at the start of a restart cycle (later

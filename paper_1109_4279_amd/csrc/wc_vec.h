@@ -51,23 +51,29 @@ WC_D void st64(double2* base, const VecSite& v, const Spinor<double>& p) {
   SpinorIO<P_F64>::store(FieldRef{(void*)(base + v.off * 12), nullptr, v.V}, v.s, p);
 }
 
-// FGCR Krylov basis vectors in their storage QP (F64, or F32 for the single-precision
-// recursion), read non-temporally and widened to FP64, or stored from FP64.
-template <int QP> WC_D Spinor<double> ldq_nt(const void* base, const VecSite& v);
-template <> WC_D Spinor<double> ldq_nt<P_F64>(const void* base, const VecSite& v) {
-  return ld64_nt((const double2*)base, v);
-}
-template <> WC_D Spinor<double> ldq_nt<P_F32>(const void* base, const VecSite& v) {
-  const gptr_t<gf4v> p = (gptr_t<gf4v>)((const float4*)base + v.off * 6);
-  Spinor<double> o;
+// FGCR Krylov vectors in their storage QP (F64, or F32 for the single-precision recursion),
+// widened to FP64 (NT: non-temporal loads, for the basis that Gram-Schmidt streams), or
+// stored from FP64.
+template <int QP, bool NT = false> WC_D Spinor<double> ldq(const void* base, const VecSite& v) {
+  if constexpr (QP == P_F64) {
+    return NT ? ld64_nt((const double2*)base, v) : ld64((const double2*)base, v);
+  } else {
+    const gptr_t<gf4v> p = (gptr_t<gf4v>)((const float4*)base + v.off * 6);
+    Spinor<double> o;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const gf4v x = __builtin_nontemporal_load(p + (size_t)k * v.V + v.s);
-    o.c[(2 * k) / 3][(2 * k) % 3] = {double(x.x), double(x.y)};
-    o.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {double(x.z), double(x.w)};
+    for (int k = 0; k < 6; ++k) {
+      gf4v x;
+      if constexpr (NT)
+        x = __builtin_nontemporal_load(p + (size_t)k * v.V + v.s);
+      else
+        x = p[(size_t)k * v.V + v.s];
+      o.c[(2 * k) / 3][(2 * k) % 3] = {double(x.x), double(x.y)};
+      o.c[(2 * k + 1) / 3][(2 * k + 1) % 3] = {double(x.z), double(x.w)};
+    }
+    return o;
   }
-  return o;
 }
+template <int QP> WC_D Spinor<double> ldq_nt(const void* base, const VecSite& v) { return ldq<QP, true>(base, v); }
 template <int QP> WC_D void stq(void* base, const VecSite& v, const Spinor<double>& p);
 template <> WC_D void stq<P_F64>(void* base, const VecSite& v, const Spinor<double>& p) { st64((double2*)base, v, p); }
 template <> WC_D void stq<P_F32>(void* base, const VecSite& v, const Spinor<double>& p) {

@@ -98,7 +98,11 @@ def test_fgcr_iterative_refinement_matches_oracle(basis, drop):
     an F32 basis means 1e-6); an F32 basis is stored rounded and the residual is updated
     with the stored vectors.  Iterations within one and restarts equal to the oracle's run
     of the same reading, the true residual after every restart following the oracle's, and
-    the answer the dense solve's within cond * tol."""
+    the answer the dense solve's within cond * tol.  With the F32 basis the restart
+    residuals also carry the single-precision rounding of D phi_k, formed in FP32 arithmetic
+    here and rounded from FP64 in the oracle: each side's part of the true residual is up to
+    about 2^-24 sum |c_k| <= 2^-24 sqrt(16) of the cycle's starting residual, so the two may
+    differ by 4e-7 of it beyond the 20 %."""
     dims, block, m0, csw = (4, 4, 4, 4), (2, 2, 2, 2), 0.0, 1.0
     lat = lattice(dims, block, m0, csw)
     b = synth.gaussian_spinor(dims)
@@ -110,8 +114,9 @@ def test_fgcr_iterative_refinement_matches_oracle(basis, drop):
     assert s["status"] == 0 and ref.converged and ref.restarts >= 2
     assert abs(s["iters"] - ref.iters) <= 1
     assert s["restarts"] == ref.restarts
-    for got, want in zip(s["res_hist"][:-1], ref.history[1:-1]):
-        assert got == pytest.approx(want, rel=0.2)
+    slack = 4e-7 if basis == "f32" else 0.0
+    for got, want, start in zip(s["res_hist"][:-1], ref.history[1:-1], ref.history[:-2]):
+        assert abs(got - want) <= 0.2 * want + slack * start
     x = to_np(x)
     assert _true_res(dims, m0, csw, x, b) <= 1e-10
     M = dense.assemble(gauge(dims), A)
