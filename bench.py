@@ -547,7 +547,8 @@ def near_critical_quenched(wc, torch, dev, block):
     stages, the second 0.02 above the first estimate), then FGCR(16), FGCR(32) and
     FGMRES-DR(32, 10) on a Gaussian source at 0.02, 0.005 and 0.001 above it (FP32 even/odd
     SAP, FP64 outer, tol 1e-10, maxit 3000): the regime of Fig. 1, where restarted GCR slows
-    down and deflated restarts keep the low modes."""
+    down and deflated restarts keep the low modes.  FGCR(32) also runs with the
+    single-precision recursion (F32 basis) to show what it does near the critical mass."""
     import synth
     from synth import quenched
     t0 = time.perf_counter()
@@ -580,6 +581,7 @@ def near_critical_quenched(wc, torch, dev, block):
 
         run("fgcr_16", lambda: lat.solve(b, check=False, nkv=16, **kw))
         run("fgcr_32", lambda: lat.solve(b, check=False, nkv=32, **kw))
+        run("fgcr_32_f32_basis", lambda: lat.solve(b, check=False, nkv=32, basis_prec="f32", **kw))
         run("fgmres_dr_32_10", lambda: lat.solve_fgmres_dr(b, k=10, check=False, nkv=32, **kw))
         r["speedup_dr_vs_fgcr_32"] = r["fgcr_32"]["ms"] / r["fgmres_dr_32_10"]["ms"]
         rec[f"dm_{dm}"] = r

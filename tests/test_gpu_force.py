@@ -35,11 +35,15 @@ def test_link_grad_full_size_16c32():
     assert rel(G, -2.0 * np.conj(np.swapaxes(K, -1, -2))) < 1e-12
 
 
-def test_force_4444_against_oracle_and_finite_differences():
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_force_4444_against_oracle_and_finite_differences(basis):
+    """The force from the library's two solves (also with the single-precision recursion of
+    an F32 basis: its FP64 restarts still reach 1e-13) against the dense-LU oracle force and
+    the finite-difference golden file."""
     dims, block, m0, csw = (4, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
     lat = lattice(dims, block, m0, csw)
     phi = synth.gaussian_spinor(dims, seed=synth.FORCE_PHI_SEED)
-    F, Y, X, st = lat.force(to_dev(phi), tol=1e-13, sap_prec="f64")
+    F, Y, X, st = lat.force(to_dev(phi), tol=1e-13, sap_prec="f64", basis_prec=basis)
     F = to_np(F)
     U, A = gauge(dims), clover(dims, m0, csw)
     M = dense.assemble(U, A)
@@ -57,13 +61,15 @@ def test_force_4444_against_oracle_and_finite_differences():
         assert np.linalg.norm(an - rows[:, 6]) / np.linalg.norm(rows[:, 6]) < 1e-6
 
 
-def test_force_16c32_solves_and_contraction():
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_force_16c32_solves_and_contraction(basis):
     """Force workload (16^3 x 32): both solves inside the force reach 1e-10, checked with the
-    oracle's D; the contraction itself is pinned by test_link_grad_full_size_16c32."""
+    oracle's D, with either Krylov basis; the contraction itself is pinned by
+    test_link_grad_full_size_16c32."""
     dims, block, m0, csw = (32, 16, 16, 16), (4, 4, 4, 4), -0.1, 1.0
     lat = lattice(dims, block, m0, csw)
     phi = synth.gaussian_spinor(dims, seed=synth.FORCE_PHI_SEED)
-    F, Y, X, st = lat.force(to_dev(phi), tol=1e-10, sap_prec="f32")
+    F, Y, X, st = lat.force(to_dev(phi), tol=1e-10, sap_prec="f32", basis_prec=basis)
     U, A = gauge(dims), clover(dims, m0, csw)
     Y, X, F = to_np(Y), to_np(X), to_np(F)
     r1 = dirac.norm(phi - dirac.apply_Ddag(U, A, Y)) / dirac.norm(phi)
