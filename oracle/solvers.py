@@ -126,11 +126,12 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
     |r| / |b| <= tol, else the recursion restarts from that residual.
 
     Iterative refinement (Sec. 4: the recursion in single precision, the residual and the
-    solution in double precision at each restart), in the reading taken here: D phi_k and the
-    normalised chi_k are held in `basis` (np.complex64 for single precision: the product
-    rounded, each component) and the residual is updated with chi_k as held, so that D phi_k
-    and the stored vectors carry the single precision and the Gram-Schmidt arithmetic stays
-    double; with drop > 0 a cycle also ends once the recursive |r| <= drop times the
+    solution in double precision at each restart), in the reading taken here: D phi_k, the
+    normalised chi_k and the recursive residual are held in `basis` (np.complex64 for single
+    precision: each component rounded; the residual when the cycle takes over the recomputed
+    one and after every update) and the residual is updated with chi_k as held, so that
+    what the recursion stores carries the single precision and the Gram-Schmidt arithmetic
+    stays double; with drop > 0 a cycle also ends once the recursive |r| <= drop times the
     recomputed |r| it started from."""
     bnorm = norm(b)
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -144,6 +145,7 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
         if iters >= maxit:
             return FGCRResult(x, False, iters, restarts, history)
         r_start = norm(r)
+        r = r.astype(basis).astype(np.complex128)
         phis, chis = [], []
         a = np.zeros((nkv, nkv), dtype=np.complex128)
         bk = np.zeros(nkv)
@@ -159,7 +161,7 @@ def fgcr(apply_op, precond, b, tol: float = 1e-10, nkv: int = 16, maxit: int = 1
             chi = chi / bk[k]
             ck[k] = dot(chi, r)
             chi = chi.astype(basis).astype(np.complex128)
-            r = r - ck[k] * chi
+            r = (r - ck[k] * chi).astype(basis).astype(np.complex128)
             phis.append(phi)
             chis.append(chi)
             k_done = k + 1
