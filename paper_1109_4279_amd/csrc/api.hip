@@ -291,7 +291,8 @@ struct Batch {
   int pw = 4 * NKV_MAX;  // partial-sum width (at most RWG: sum_partials)
   // solver state
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
-  Field w;  // FGCR with an F32 basis: the direction D phi_k (F32) before its Gram-Schmidt
+  Field w;    // FGCR with an F32 basis: the direction D phi_k (F32) before its Gram-Schmidt
+  Field r32;  // ... and the recursion's residual between restarts (F32)
   DevBuf d_chi, d_phi;
   // FGCR directions in the preconditioner's storage, and their pointer tables
   Field dir[NKV_MAX];
@@ -739,6 +740,7 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.fuse_sap = 0;
   a.q = B.d_chi.as<void* const>();
   a.w = nullptr;
+  a.rq = a.r;
   a.drop2 = s.drop2;
   return a;
 }
@@ -755,7 +757,10 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   std::vector<double2*> pc(NKV_MAX, nullptr), pp(NKV_MAX, nullptr);
   std::vector<void*> pd(NKV_MAX, nullptr);
   std::vector<float*> pds(NKV_MAX, nullptr);
-  if (fgcr && s.basis_prec != P_F64) B.w.ensure(P_F32, n);
+  if (fgcr && s.basis_prec != P_F64) {
+    B.w.ensure(P_F32, n);
+    B.r32.ensure(P_F32, n);
+  }
   for (int k = 0; k < s.nkv; ++k) {
     B.chi[k].ensure(fgcr ? s.basis_prec : P_F64, n);
     pc[k] = B.chi[k].d.as<double2>();
@@ -800,6 +805,9 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
   const int* skip = B.skip.as<int>();
   mark(tm, PH_BLAS, st);
   const bool f64_basis = s.basis_prec == P_F64;
+  // the recursion's residual: r itself with an FP64 basis; with an F32 one, an F32 copy that
+  // the cycle's first conversion writes from the FP64 true residual
+  va.rq = f64_basis ? B.r.data() : B.r32.data();
   for (int k = 0; k < s.nkv; ++k) {
     va.k = k;
     // the direction D phi_k: chi_k itself with an FP64 basis, else the F32 buffer w from
@@ -812,7 +820,7 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
       VecLaunch vs = va;
       vs.sp = B.sap_rho.data();
       vs.sp_sc = B.sap_rho.scale();
-      launch_to_sap(s.sap_prec, vs, gv, st);
+      launch_to_sap(s.sap_prec, s.basis_prec, vs, gv, st);
     }
     run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
     mark(tm, PH_SAP, st);
@@ -870,6 +878,7 @@ static std::string graph_key(const Batch& B, const SolveSetup& s) {
   add(B.b.data());
   add(B.r.data());
   add(B.w.data());
+  add(B.r32.data());
   for (int i = 0; i < s.nkv; ++i) {
     add(B.chi[i].data());
     add(B.phi[i].data());

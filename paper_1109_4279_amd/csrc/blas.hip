@@ -13,7 +13,7 @@ namespace wc {
 
 // ------------------------------------------------------------------ conversions
 
-template <int P>
+template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_to_sap(VecLaunch a) {
   typedef typename Real<P>::T R;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
@@ -21,6 +21,7 @@ __global__ __launch_bounds__(WG) void k_to_sap(VecLaunch a) {
     if (a.skip[v.sys] || !v.valid) continue;
     const double inv = 1.0 / sqrt(a.sys[v.sys].rnorm2);
     Spinor<double> r = ld64(a.r, v);
+    if (QP != P_F64) stq<QP>(a.rq, v, r);
     Spinor<R> o;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
     if (a.skip[v.sys]) continue;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Spinor<double> ck = ldq<QP>(a.w, v);
-    Spinor<double> r = ld64(a.r, v);
+    Spinor<double> r = ldq<QP>(a.rq, v);
     if (!v.valid) {
       zero(ck);
       zero(r);
@@ -123,9 +124,9 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
 }
 
 // chi_k <- (w - sum_l a_lk chi_l) / b_k, stored in QP;  r <- r - c_k chi_k with chi_k as
-// stored (so that r stays the residual of the stored basis: the FP64 recursion then only
-// carries the rounding of its own arithmetic);  partial |r|^2; with fuse_sap also the next
-// preconditioner input r / |r_k| (storage P).
+// stored (so that r stays the residual of the stored basis), r held in QP too (the FP64 r
+// with an FP64 basis, its F32 copy rq with an F32 one);  partial |r|^2 of r as stored; with
+// fuse_sap also the next preconditioner input r / |r_k| (storage P).
 // A system flagged by the reduction for a second pass (S.reorth) instead stores
 // chi_k' = w - sum_l a_lk chi_l in w (storage QP) and the partial sums of the second pass,
 //   a2_l = <chi_l, chi_k'> (l < k), |chi_k'|^2 and <chi_k', r>,
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
         stq<QP>(a.w, v, ck);
       else
         zero(ck);
-      Spinor<double> r = ld64(a.r, v);
+      Spinor<double> r = ldq<QP>(a.rq, v);
       if (!v.valid) zero(r);
       auto put = [&](int j, double x) {
         x = wave_sum(x);
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
     const cplx<double> mc = {-S.ck[k].x, -S.ck[k].y};
     double vals[1] = {0.0};
     if (v.valid) {
-      Spinor<double> r = ld64(a.r, v);
+      Spinor<double> r = ldq<QP>(a.rq, v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -210,12 +211,14 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          cmac(r.c[i][c], mc, ck.c[i][c]);
-          vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
-        }
+        for (int c = 0; c < 3; ++c) cmac(r.c[i][c], mc, ck.c[i][c]);
+      round_to<QP>(r);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
       stq<QP>(a.q[k], v, ck);
-      st64(a.r, v, r);
+      stq<QP>(a.rq, v, r);
       if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
     put_partial<1>(a, v, vals, lds);
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
     const cplx<double> mc = {-S.ck[k].x, -S.ck[k].y};
     double vals[1] = {0.0};
     if (v.valid) {
-      Spinor<double> r = ld64(a.r, v);
+      Spinor<double> r = ldq<QP>(a.rq, v);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -257,12 +260,14 @@ __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          cmac(r.c[i][c], mc, ck.c[i][c]);
-          vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
-        }
+        for (int c = 0; c < 3; ++c) cmac(r.c[i][c], mc, ck.c[i][c]);
+      round_to<QP>(r);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vals[0] += r.c[i][c].re * r.c[i][c].re + r.c[i][c].im * r.c[i][c].im;
       stq<QP>(a.q[k], v, ck);
-      st64(a.r, v, r);
+      stq<QP>(a.rq, v, r);
       if (a.fuse_sap) store_sap_input<P>(a, v, r);
     }
     put_partial<1>(a, v, vals, lds);
@@ -519,13 +524,19 @@ template <class F> static void launch_vec(F kern, const VecLaunch& a, int grid, 
   hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, st, a);
 }
 
-void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st) {
+template <int QP> static void to_sap_q(int prec, const VecLaunch& a, int grid, hipStream_t st) {
   switch (prec) {
-    case P_F64: launch_vec(k_to_sap<P_F64>, a, grid, st); break;
-    case P_F32: launch_vec(k_to_sap<P_F32>, a, grid, st); break;
-    case P_F16: launch_vec(k_to_sap<P_F16>, a, grid, st); break;
-    default: launch_vec(k_to_sap<P_BF16>, a, grid, st); break;
+    case P_F64: launch_vec(k_to_sap<P_F64, QP>, a, grid, st); break;
+    case P_F32: launch_vec(k_to_sap<P_F32, QP>, a, grid, st); break;
+    case P_F16: launch_vec(k_to_sap<P_F16, QP>, a, grid, st); break;
+    default: launch_vec(k_to_sap<P_BF16, QP>, a, grid, st); break;
   }
+}
+void launch_to_sap(int prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st) {
+  if (basis_prec == P_F32)
+    to_sap_q<P_F32>(prec, a, grid, st);
+  else
+    to_sap_q<P_F64>(prec, a, grid, st);
 }
 void launch_gs_dots(int basis_prec, const VecLaunch& a, int grid, hipStream_t st) {
   if (basis_prec == P_F32)

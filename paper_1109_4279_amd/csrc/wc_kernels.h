@@ -170,12 +170,14 @@ struct VecLaunch {
   // basis, chi_k itself: the update then overwrites it in place)
   void* const* q;
   void* w;
+  void* rq;                // the recursion's residual in the basis storage (with an FP64 basis, r)
   double drop2;            // a cycle ends once |r|^2 <= drop2 x its starting true |r|^2 (0: never)
 };
 // eta(P) = r / |r|, the preconditioner's input at the start of a restart cycle (later
 // steps get theirs from the residual update); the FGCR direction phi_k is the
 // preconditioner's output as stored (GCR is invariant to the scale of a direction)
-void launch_to_sap(int prec, const VecLaunch& a, int grid, hipStream_t st);
+// (with an F32 basis also the recursion's F32 residual rq = r, rounded)
+void launch_to_sap(int prec, int basis_prec, const VecLaunch& a, int grid, hipStream_t st);
 // Gram-Schmidt kernels for a basis stored in basis_prec (P_F64 or P_F32)
 void launch_gs_dots(int basis_prec, const VecLaunch& a, int grid, hipStream_t st);  // <chi_l, w>, <chi_l, r>, |w|^2, <w, r>
 // chi_k = (w - sum a_lk chi_l)/b_k in the basis storage; r -= c_k chi_k (chi_k as stored);
