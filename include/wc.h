@@ -82,10 +82,10 @@ typedef struct {
   int timing;    /* 1: run the FGCR restart cycles eagerly with HIP events between the
                     phases and report t_sap/t_dirac/t_blas (slower; FGCR only) */
   int basis_prec; /* storage of the FGCR Krylov basis chi_l: WC_F64, or WC_F32 for the
-                    single-precision recursion of Sec. 4 (iterative refinement: D phi_k in
-                    FP32 arithmetic, Gram-Schmidt against the F32-stored vectors in FP64
-                    arithmetic between restarts; the residual, the solution and the true
-                    residual at every restart in FP64).  FGMRES-DR: WC_F64 only.
+                    single-precision recursion of Sec. 4 (iterative refinement: between
+                    restarts D phi_k in FP32 arithmetic, the basis and the recursive
+                    residual stored in F32, Gram-Schmidt arithmetic in FP64; the solution
+                    and the true residual at every restart in FP64).  FGMRES-DR: WC_F64 only.
                     Errors: WC_ERR_ARG */
   double drop;   /* a restart cycle also ends once its recursive residual is `drop` times
                     the FP64 true residual it started from; 0: none with an FP64 basis,
