@@ -293,6 +293,7 @@ struct Batch {
   Field x, b, r, chi[NKV_MAX], phi[NKV_MAX];
   Field w;    // FGCR with an F32 basis: the direction D phi_k (F32) before its Gram-Schmidt
   Field r32;  // ... and the recursion's residual between restarts (F32)
+  DevBuf dead;  // FGCR: cycle-ended flag and the counts behind it (VecLaunch::dead)
   DevBuf d_chi, d_phi;
   // FGCR directions in the preconditioner's storage, and their pointer tables
   Field dir[NKV_MAX];
@@ -537,7 +538,7 @@ static int dirac_stage_mode(const Batch& B, int prec, int nr) {
 }
 
 static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, const Field* y, double* partials,
-                      const int* skip, int dagger, int block, hipStream_t st) {
+                      const int* skip, int dagger, int block, hipStream_t st, const int* dead = nullptr) {
   const LatDesc* L = B.lats(prec, st);
   DiracLaunch a;
   a.lats = L;
@@ -553,6 +554,7 @@ static void run_dirac(Batch& B, int prec, int nr, const Field& in, Field& out, c
   a.skip = skip;
   a.dagger = dagger;
   a.block = block;
+  a.dead = dead;
   // (a tile of nr rhs that does not fit a work-group's LDS runs unstaged)
   const int mode = dirac_stage_mode(B, prec, nr);
   for (int sel : (mode == 2 ? std::array<int, 2>{1, 2} : std::array<int, 2>{0, -1})) {
@@ -579,7 +581,7 @@ static int sap_cache_mode(const Batch& B, int nitems) {
 // odd_rho: residual on odd sites for the even/odd solver (see SapLaunch::odd_rho)
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
                               const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st,
-                              int odd_rho = 0) {
+                              int odd_rho = 0, const int* dead = nullptr) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
   require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol, 0) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
@@ -598,6 +600,7 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
     SapLaunch a;
     a.lats = L;
     a.items = it.d.as<WorkItem>();
+    a.dead = dead;
     a.nitems = it.n;
     a.colour = colour;
     a.nmr = nmr;
@@ -630,14 +633,14 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
 
 // ncy Schwarz cycles on rho (source), accumulating psi
 static void run_sap(Batch& B, int prec, int nr, int ncy, int nmr, Field& rho, Field& z, Field& psi, const int* skip,
-                    int eo, hipStream_t st) {
+                    int eo, hipStream_t st, const int* dead = nullptr) {
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
       const bool last = (cy == ncy - 1);
       // the SAP's residual field is private: odd sites are read from it only on the first
       // visit of a block (later they hold the zero the previous solve left) and never stored
       run_sap_halfsweep(B, prec, nr, c, nmr, rho, z, psi, skip, cy == 0, !(cy == 0 && c == 0), !last,
-                        !(last && c == 1), eo, st, cy == 0 ? 1 : 2);
+                        !(last && c == 1), eo, st, cy == 0 ? 1 : 2, dead);
     }
 }
 
@@ -741,6 +744,7 @@ static VecLaunch vec_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   a.q = B.d_chi.as<void* const>();
   a.w = nullptr;
   a.rq = a.r;
+  a.dead = B.dead.p ? B.dead.as<int>() : nullptr;
   a.drop2 = s.drop2;
   return a;
 }
@@ -786,6 +790,10 @@ static void prepare_solver(Batch& B, const SolveSetup& s, bool fgcr = true) {
   B.sap_psi.ensure(s.sap_prec, n);
   B.sys.ensure(sizeof(SysState) * B.nsys);
   B.skip.ensure(sizeof(int) * B.nsys);
+  // the cycle-ended flag and counts start at zero (a solve that ended abnormally could have
+  // left them set); cleared here, outside any captured cycle
+  B.dead.ensure(3 * sizeof(int));
+  HIPCK(hipMemset(B.dead.p, 0, 3 * sizeof(int)));
   B.hist.ensure(sizeof(double) * HIST_MAX * B.nsys);
   // everything a captured cycle touches must exist before capture starts
   B.lats(P_F64, nullptr);
@@ -822,14 +830,15 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
       vs.sp_sc = B.sap_rho.scale();
       launch_to_sap(s.sap_prec, s.basis_prec, vs, gv, st);
     }
-    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
+    const int* dead = va.dead;
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st, dead);
     mark(tm, PH_SAP, st);
     // w = D phi_k: FP64 arithmetic with an FP64 basis, FP32 (the single-precision
     // recursion) with an F32 one
     if (f64_basis)
-      run_dirac(B, P_F64, s.nr_d, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
+      run_dirac(B, P_F64, s.nr_d, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st, dead);
     else
-      run_dirac(B, P_F32, s.nr_d32, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st);
+      run_dirac(B, P_F32, s.nr_d32, B.dir[k], wk, nullptr, nullptr, skip, 0, 0, st, dead);
     mark(tm, PH_DIRAC, st);
     // classical Gram-Schmidt: all inner products, then the update of chi_k and r (and the
     // next preconditioner input); a system whose first pass cancelled takes a second pass
@@ -891,7 +900,7 @@ static std::string graph_key(const Batch& B, const SolveSetup& s) {
     add(f->data());
     add(f->scale());
   }
-  for (const DevBuf* d : {&B.sys, &B.skip, &B.partials, &B.hist, &B.d_chi, &B.d_phi, &B.d_arn_v, &B.arn,
+  for (const DevBuf* d : {&B.dead, &B.sys, &B.skip, &B.partials, &B.hist, &B.d_chi, &B.d_phi, &B.d_arn_v, &B.arn,
                           &B.sys_part, &B.sys_nchunks, &B.d_lats[P_F64], &B.d_lats[s.sap_prec], &B.d_lats[P_F32]})
     add(d->p);
   add(B.arn_vlast.data());
@@ -1052,6 +1061,7 @@ static VecLaunch arn_launch(Batch& B, const SolveSetup& s, hipStream_t st) {
   VecLaunch a = vec_launch(B, s, st);
   a.chi = B.d_arn_v.as<double2* const>();
   a.arn = B.arn.as<ArnState>();
+  a.dead = nullptr;
   return a;
 }
 

@@ -16,6 +16,8 @@ namespace wc {
 template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_to_sap(VecLaunch a) {
   typedef typename Real<P>::T R;
+  // a new cycle: its launches run again
+  if (a.dead && blockIdx.x == 0 && threadIdx.x == 0) a.dead[0] = 0;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
     if (a.skip[v.sys] || !v.valid) continue;
@@ -66,6 +68,7 @@ WC_D void store_sap_input(const VecLaunch& a, const VecSite& v, const Spinor<dou
 template <int QP>
 __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (4 * NKV_MAX + 4)];
+  if (cycle_dead(a.dead)) return;
   const int k = a.k;
   const int nv = 4 * k + 3;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
@@ -134,6 +137,7 @@ __global__ __launch_bounds__(WG) void k_gs_dots(VecLaunch a) {
 template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
   __shared__ double lds[(WG / 64) * (2 * NKV_MAX + 4)];
+  if (cycle_dead(a.dead)) return;
   const int k = a.k;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
@@ -232,6 +236,7 @@ __global__ __launch_bounds__(WG) void k_gs_update(VecLaunch a) {
 template <int P, int QP>
 __global__ __launch_bounds__(WG) void k_gs_update2(VecLaunch a) {
   __shared__ double lds[(WG / 64)];
+  if (cycle_dead(a.dead)) return;
   const int k = a.k;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     VecSite v = vec_site(a, it0);
@@ -371,8 +376,7 @@ WC_D void gs_breakdown(SysState& S, int* skip, int sys, int k) {
   skip[sys] = 1;
 }
 
-__global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
-  __shared__ double lds[RWG];
+WC_D void reduce_sys(int op, const VecLaunch& a, const int* sys_part, const int* sys_nchunks, double* lds) {
   const int sys = blockIdx.x;
   SysState& S = a.sys[sys];
   const int nv = op == RED_GS ? 4 * a.k + 3 : (op == RED_GS2 ? 2 * a.k + 3 : 1);
@@ -497,6 +501,25 @@ __global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* 
       a.skip[sys] = S.converged;
       break;
     }
+  }
+}
+
+// One work-group per system.  After the residual-norm reduction of an FGCR cycle (a.dead
+// set) every work-group adds whether its system has ended the cycle; the last one to arrive
+// raises a.dead[0] when all have (the cycle's remaining launches then return at once) and
+// clears the two counts for the next launch.
+__global__ __launch_bounds__(RWG) void k_reduce(int op, VecLaunch a, const int* sys_part, const int* sys_nchunks) {
+  __shared__ double lds[RWG];
+  reduce_sys(op, a, sys_part, sys_nchunks, lds);
+  if (op != RED_RNORM || !a.dead || threadIdx.x != 0) return;
+  __threadfence();
+  atomicAdd(&a.dead[2], a.skip[blockIdx.x] != 0 ? 1 : 0);
+  __threadfence();
+  if (atomicAdd(&a.dead[1], 1) == (int)gridDim.x - 1) {
+    const int ended = atomicAdd(&a.dead[2], 0);
+    atomicExch(&a.dead[2], 0);
+    atomicExch(&a.dead[1], 0);
+    atomicExch(&a.dead[0], ended == (int)gridDim.x ? 1 : 0);
   }
 }
 

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(WG) void k_dirac(DiracLaunch a) {
   extern __shared__ double stage_d[];
   cplx<R>* st_sp = (cplx<R>*)stage_d;        // [NR][12][WG] input spinors of the tile (unscaled)
   R* st_sc = (R*)(st_sp + NR * 12 * WG);     // [NR][WG] their site scales
+  if (cycle_dead(a.dead)) return;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     const WorkItem w = load_uniform(a.items, xcd_remap(it0, a.nitems));
     const LatDesc L = load_uniform(a.lats, w.lat);

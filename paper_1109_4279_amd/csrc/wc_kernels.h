@@ -25,9 +25,13 @@ struct DiracLaunch {
   int dagger;          // apply gamma5 D gamma5
   int block;           // Dirichlet-block operator instead of the full one
   int stage;           // the items' lattices have 256-site tiles: stage each tile's input in LDS
-  int in_prec;         // storage precision of `in` (may differ from the launch's only for FP64)
+  int in_prec;         // storage precision of `in` (may differ from the launch's for FP64 and FP32)
+  // FGCR cycle: dead[0] != 0 once every system has ended the cycle (the launch then does nothing)
+  const int* dead = nullptr;
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
+// a launch of an FGCR cycle after every system has ended it
+WC_D bool cycle_dead(const int* dead) { return dead && gld_i32(dead, 0) != 0; }
 size_t dirac_stage_lds_bytes(int prec, int nr);  // dynamic LDS of a staged D_w launch
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;       // LDS a gfx950 work-group may allocate
 
@@ -56,6 +60,7 @@ struct SapLaunch {
   // rows of length eo_rows
   int border_entries;
   int eo_rows;
+  const int* dead = nullptr;  // as DiracLaunch::dead
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
@@ -171,6 +176,10 @@ struct VecLaunch {
   void* const* q;
   void* w;
   void* rq;                // the recursion's residual in the basis storage (with an FP64 basis, r)
+  // FGCR cycle: [0] != 0 once every system has ended the cycle (the residual-norm reduction
+  // sets it, the cycle's first conversion clears it; Gram-Schmidt then does nothing), [1] and
+  // [2] that reduction's arrival and ended-system counts (zero between launches); or null
+  int* dead;
   double drop2;            // a cycle ends once |r|^2 <= drop2 x its starting true |r|^2 (0: never)
 };
 // eta(P) = r / |r|, the preconditioner's input at the start of a restart cycle (later
