@@ -102,6 +102,28 @@ def test_fgcr_multi_rhs_point_sources():
     assert rel(x[5], to_np(one)) < 1e-8
 
 
+@pytest.mark.parametrize("basis", ["f64", "f32"])
+def test_batched_systems_run_their_own_cycles(basis):
+    """Systems of one batch that end their cycles at different iterations (point sources and
+    Gaussian sources; with the F32 basis, cycles that end at the drop) each take exactly the
+    iterations and restarts of their own single-rhs solve, and the same answer: the launches
+    of a cycle stop early only once every system of the batch has ended it."""
+    dims, block, m0, csw = (8, 4, 4, 4), (2, 2, 2, 2), -0.1, 1.0
+    lat = lattice(dims, block, m0, csw)
+    pts = synth.point_sources(dims)
+    b = np.stack([pts[0], synth.gaussian_spinor(dims, seed=61), pts[7], synth.gaussian_spinor(dims, seed=62)])
+    kw = dict(tol=1e-10, sap_prec="f32", eo=1, nkv=8, basis_prec=basis)
+    x, st = lat.solve(to_dev(b), **kw)
+    x = to_np(x)
+    counts = set()
+    for r in range(4):
+        x1, s1 = lat.solve(to_dev(b[r]), **kw)
+        assert (st[r]["iters"], st[r]["restarts"]) == (s1[0]["iters"], s1[0]["restarts"])
+        assert rel(x[r], to_np(x1)) < 1e-12
+        counts.add(st[r]["iters"])
+    assert len(counts) > 1  # the systems did end their cycles at different iterations
+
+
 @pytest.mark.parametrize("basis,drop", [("f64", 1e-5), ("f32", 0.0), ("f32", 1e-3)])
 def test_fgcr_iterative_refinement_matches_oracle(basis, drop):
     """Iterative refinement (Sec. 4) on 4^4 with FP64 SAP: a cycle also ends once its
