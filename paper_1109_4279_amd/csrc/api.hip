@@ -581,7 +581,7 @@ static int sap_cache_mode(const Batch& B, int nitems) {
 // odd_rho: residual on odd sites for the even/odd solver (see SapLaunch::odd_rho)
 static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, Field& rho, Field& z, Field& psi,
                               const int* skip, int first, int border, int wrho, int wz, int eo, hipStream_t st,
-                              int odd_rho = 0, const int* dead = nullptr) {
+                              int odd_rho = 0) {
   require(nr >= 1 && nr <= (prec == P_F64 ? 1 : 2), WC_ERR_ARG, "block-solver rhs tile out of range");
   require((eo ? sap_eo_lds_bytes(prec, nr, B.max_bvol, 0) : sap_lds_bytes(prec, nr, B.sap_threads())) <= 65536,
           WC_ERR_GEOMETRY, "block too large for LDS");
@@ -600,7 +600,6 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
     SapLaunch a;
     a.lats = L;
     a.items = it.d.as<WorkItem>();
-    a.dead = dead;
     a.nitems = it.n;
     a.colour = colour;
     a.nmr = nmr;
@@ -633,14 +632,14 @@ static void run_sap_halfsweep(Batch& B, int prec, int nr, int colour, int nmr, F
 
 // ncy Schwarz cycles on rho (source), accumulating psi
 static void run_sap(Batch& B, int prec, int nr, int ncy, int nmr, Field& rho, Field& z, Field& psi, const int* skip,
-                    int eo, hipStream_t st, const int* dead = nullptr) {
+                    int eo, hipStream_t st) {
   for (int cy = 0; cy < ncy; ++cy)
     for (int c = 0; c < 2; ++c) {
       const bool last = (cy == ncy - 1);
       // the SAP's residual field is private: odd sites are read from it only on the first
       // visit of a block (later they hold the zero the previous solve left) and never stored
       run_sap_halfsweep(B, prec, nr, c, nmr, rho, z, psi, skip, cy == 0, !(cy == 0 && c == 0), !last,
-                        !(last && c == 1), eo, st, cy == 0 ? 1 : 2, dead);
+                        !(last && c == 1), eo, st, cy == 0 ? 1 : 2);
     }
 }
 
@@ -831,7 +830,7 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
       launch_to_sap(s.sap_prec, s.basis_prec, vs, gv, st);
     }
     const int* dead = va.dead;
-    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st, dead);
+    run_sap(B, s.sap_prec, s.nr_s, s.ncy, s.nmr, B.sap_rho, B.sap_z, B.dir[k], skip, s.eo, st);
     mark(tm, PH_SAP, st);
     // w = D phi_k: FP64 arithmetic with an FP64 basis, FP32 (the single-precision
     // recursion) with an F32 one

@@ -24,7 +24,6 @@ __global__ __launch_bounds__(256) void k_sap_mr(SapLaunch a) {
   double* red = smem_d;                                   // SAP_MAX_WAVES * 3 * NR doubles
   cplx<R>* lds = (cplx<R>*)(smem_d + SAP_MAX_WAVES * 3 * NR);  // [NR][12][bvol]
 
-  if (cycle_dead(a.dead)) return;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     const WorkItem w = a.items[xcd_remap(it0, a.nitems)];
     const LatDesc& L = a.lats[w.lat];

@@ -385,7 +385,6 @@ __global__ __launch_bounds__(64 * EO_MAX_WAVES) void k_sap_eo(SapLaunch a) {
   cplx<R>* lds = (cplx<R>*)(smem_d + EO_MAX_WAVES * 3 * NR);  // [NR][12][bvol]
   cplx<R>* bord = lds + (size_t)NR * 12 * a.eo_rows;           // [NR][12][border entries]
 
-  if (cycle_dead(a.dead)) return;
   const int s = threadIdx.x & 1;
   const int pr = threadIdx.x >> 1;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {

@@ -27,7 +27,6 @@ __global__ __launch_bounds__(NR * 256) void k_sap_mr_lds(SapLaunch a) {
   float* csc = lsc + SL_BV;                                     // clover scales [2][256]
   cplx<R>* ex = (cplx<R>*)(csc + 2 * SL_BV);                    // residual exchange [NR][12][256]
 
-  if (cycle_dead(a.dead)) return;
   for (int it0 = blockIdx.x; it0 < a.nitems; it0 += gridDim.x) {
     const WorkItem w = a.items[xcd_remap(it0, a.nitems)];
     const LatDesc& L = a.lats[w.lat];

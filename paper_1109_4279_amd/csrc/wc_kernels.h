@@ -26,7 +26,10 @@ struct DiracLaunch {
   int block;           // Dirichlet-block operator instead of the full one
   int stage;           // the items' lattices have 256-site tiles: stage each tile's input in LDS
   int in_prec;         // storage precision of `in` (may differ from the launch's for FP64 and FP32)
-  // FGCR cycle: dead[0] != 0 once every system has ended the cycle (the launch then does nothing)
+  // FGCR cycle: dead[0] != 0 once every system has ended the cycle (the launch then does
+  // nothing).  The block solvers do not take it: the check alone moved scalar-register spill
+  // code into the even/odd solver's MR loop (+13 instructions per step, half-sweep 1538 ->
+  // 1566 us), more than their launches after the end of a cycle cost
   const int* dead = nullptr;
 };
 void launch_dirac(int prec, int nr, const DiracLaunch& a, int grid, hipStream_t st);
@@ -60,7 +63,6 @@ struct SapLaunch {
   // rows of length eo_rows
   int border_entries;
   int eo_rows;
-  const int* dead = nullptr;  // as DiracLaunch::dead
 };
 void launch_sap_mr(int prec, int nr, const SapLaunch& a, int grid, int block_threads, hipStream_t st);
 size_t sap_lds_bytes(int prec, int nr, int bvol);
@@ -177,7 +179,7 @@ struct VecLaunch {
   void* w;
   void* rq;                // the recursion's residual in the basis storage (with an FP64 basis, r)
   // FGCR cycle: [0] != 0 once every system has ended the cycle (the residual-norm reduction
-  // sets it, the cycle's first conversion clears it; Gram-Schmidt then does nothing), [1] and
+  // sets it, the cycle's first conversion clears it; D and Gram-Schmidt then do nothing), [1] and
   // [2] that reduction's arrival and ended-system counts (zero between launches); or null
   int* dead;
   double drop2;            // a cycle ends once |r|^2 <= drop2 x its starting true |r|^2 (0: never)
