@@ -169,7 +169,11 @@ class Lattice:
         return psi
 
     def solve(self, b, params: SolverParams | None = None, x0=None, stream=None, check=True, **kw):
-        """x = D^-1 b by SAP-preconditioned FGCR.  Returns (x, list of per-rhs stats dicts)."""
+        """x = D^-1 b by SAP-preconditioned FGCR.  Returns (x, list of per-rhs stats dicts).
+        Solver parameters come from `params` or the keywords (wc_solver_params' fields), e.g.
+        sap_prec="bf16", eo=1, and basis_prec="f32" for the single-precision recursion
+        between FP64 restarts (cycles then also end at a drop of the residual, 1e-6 unless
+        `drop` is given)."""
         nrhs = self._spinor(b, "b")
         p = _params(params, kw)
         if x0 is not None:
