@@ -858,7 +858,7 @@ static void enqueue_cycle(Batch& B, const SolveSetup& s, hipStream_t st, PhaseTi
   launch_backsub(va, B.nsys, st);
   launch_x_update_dir(va, gv, st);
   mark(tm, PH_BLAS, st);
-  run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+  run_dirac(B, P_F64, s.nr_d, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
   mark(tm, PH_DIRAC, st);
   launch_reduce(RED_TRUE, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   mark(tm, PH_BLAS, st);
@@ -963,7 +963,7 @@ static int fgcr_solve(Batch& B, const SolveSetup& s, bool x0_given, bool use_gra
   launch_reduce(RED_BNORM, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   if (x0_given) {
     launch_zero_if_b0(va, B.x.d.as<double2>(), gv, st);
-    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    run_dirac(B, P_F64, s.nr_d, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
     launch_reduce(RED_INITR, va, B.nsys, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   } else {
     HIPCK(hipMemsetAsync(B.x.data(), 0, spinor_bytes(P_F64, B.sites_rhs), st));
@@ -1172,7 +1172,7 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
   launch_reduce(RED_BNORM, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   if (x0_given) {
     launch_zero_if_b0(va, B.x.d.as<double2>(), gv, st);
-    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    run_dirac(B, P_F64, s.nr_d, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
     launch_reduce(RED_INITR, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
   } else {
     HIPCK(hipMemsetAsync(B.x.data(), 0, spinor_bytes(P_F64, B.sites_rhs), st));
@@ -1260,7 +1260,7 @@ static int fgmres_dr_solve(Batch& B, const SolveSetup& s, int kdefl, bool x0_giv
     HIPCK(hipMemcpyAsync(B.sys.p, hs.data(), sizeof(SysState) * n, hipMemcpyHostToDevice, st));
     HIPCK(hipStreamSynchronize(st));
     launch_x_update(va, gv, st);
-    run_dirac(B, P_F64, 1, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
+    run_dirac(B, P_F64, s.nr_d, B.x, B.r, &B.b, B.partials.as<double>(), nullptr, 0, 0, st);
     launch_reduce(RED_TRUE, va, n, B.sys_part.as<int>(), B.sys_nchunks.as<int>(), st);
     HIPCK(hipGetLastError());
     std::vector<int> mm_of(n);
