@@ -108,6 +108,9 @@ def test_default_params_and_error_text():
     assert (p.nkv, p.ncy, p.nmr, p.sap_prec, p.maxit, p.eo, p.dagger, p.stag, p.timing) == \
         (16, 5, 4, 1, 10000, 0, 0, 3, 0)
     assert abs(p.tol - 1e-10) < 1e-25
+    assert (p.basis_prec, p.drop) == (0, 0.0)  # FP64 Krylov basis, no per-cycle drop
+    q = default_params(basis_prec="f32", drop=1e-6)
+    assert (q.basis_prec, q.drop) == (1, 1e-6)
     lib = _lib.load()
     # argument errors are reported without touching a device
     ctx = ctypes.c_void_p()
