@@ -418,9 +418,11 @@ def extra_workloads(wc, torch, dev, storage, lat_c4, pts):
     lat = wc.Lattice(torch.from_numpy(synth.gauge_field(C2_DIMS)).to(dev), block=BLOCK, m0=M0, csw=CSW)
     b = torch.from_numpy(synth.gaussian_spinor(C2_DIMS)).to(dev)
     c2 = {"dirac": dirac_rates(lat, 131072, ("f64", "f32", "f16", "bf16"), iters=100)}
-    for name, sp, eo in (("fp64_mr", "f64", 0), ("fp64_eo", "f64", 1), ("mixed_f32_eo", "f32", 1)):
-        _, st, ms = timed_solve(lat, b, params(wc, sp, eo), torch)
-        c2[name] = {"ms": ms, "iters": st[0]["iters"], "true_rel_residual": st[0]["rel_true_res"]}
+    for name, sp, eo, qp in (("fp64_mr", "f64", 0, "f64"), ("fp64_eo", "f64", 1, "f64"),
+                             ("mixed_f32_eo", "f32", 1, "f64"), ("mixed_f32_eo_f32_basis", "f32", 1, "f32")):
+        _, st, ms = timed_solve(lat, b, params(wc, sp, eo, basis_prec=qp), torch)
+        c2[name] = {"ms": ms, "iters": st[0]["iters"], "restarts": st[0]["restarts"],
+                    "true_rel_residual": st[0]["rel_true_res"]}
     c2["roofline_k_sap_eo_f32_cached"] = roofline_record(lat, 131072, "f32", 1, BLOCK,
                                                           "k_sap_eo<F32, 1 rhs, cached>, 16^3x32, one colour")
     # the force of S = phi^dag (D^dag D)^-1 phi (two solves + the force kernel)
@@ -446,18 +448,21 @@ def extra_workloads(wc, torch, dev, storage, lat_c4, pts):
         la.autotune_block(params(wc, storage, True))
         lats.append(la)
         bs.append(torch.from_numpy(synth.gaussian_spinor(d, nrhs=4, seed=synth.RHS_SEED + i)).to(dev))
-    p = params(wc, storage, True)
-    wc.solve_batch(lats, bs, p)
-    (_, st), ms = sync_time(torch, lambda: wc.solve_batch(lats, bs, p))
-    single = 0.0
-    for la, bb in zip(lats, bs):
-        la.solve(bb, p)
-        _, t1 = sync_time(torch, lambda: la.solve(bb, p))
-        single += t1
-    out["uneven_batch"] = {"lattices": [list(d) for d in UNEVEN], "blocks": [list(la.block) for la in lats],
-                           "rhs_per_lattice": 4, "storage": storage, "batched_ms": ms,
-                           "separate_solves_ms": single, "max_iters": max(s["iters"] for s in st),
-                           "max_true_rel_residual": max(s["rel_true_res"] for s in st)}
+    ub = {"lattices": [list(d) for d in UNEVEN], "blocks": [list(la.block) for la in lats], "rhs_per_lattice": 4,
+          "storage": storage}
+    for qp, tag in (("f64", ""), ("f32", "_f32_basis")):
+        p = params(wc, storage, True, basis_prec=qp)
+        wc.solve_batch(lats, bs, p)
+        (_, st), ms = sync_time(torch, lambda: wc.solve_batch(lats, bs, p))
+        single = 0.0
+        for la, bb in zip(lats, bs):
+            la.solve(bb, p)
+            _, t1 = sync_time(torch, lambda: la.solve(bb, p))
+            single += t1
+        ub.update({"batched_ms" + tag: ms, "separate_solves_ms" + tag: single,
+                   "max_iters" + tag: max(s["iters"] for s in st),
+                   "max_true_rel_residual" + tag: max(s["rel_true_res"] for s in st)})
+    out["uneven_batch"] = ub
     del lats, bs
     # 32^3 x 64: every storage, and the error against an independent FP64 reference (the
     # plain MR block solver to 1e-12: another iteration than the mixed solves')
@@ -470,8 +475,9 @@ def extra_workloads(wc, torch, dev, storage, lat_c4, pts):
     nref = torch.linalg.vector_norm(xref)
     _, st, ms = timed_solve(lat, b, params(wc, "f64", False), torch)
     rec["fp64_mr"] = {"ms": ms, "iters": st[0]["iters"]}
-    for name, sp in (("fp64_eo", "f64"), ("f32", "f32"), ("f16", "f16"), ("bf16", "bf16")):
-        x, st, ms = timed_solve(lat, b, params(wc, sp, True), torch)
+    for name, sp, qp in (("fp64_eo", "f64", "f64"), ("f32", "f32", "f64"), ("f16", "f16", "f64"),
+                         ("bf16", "bf16", "f64"), ("bf16_f32_basis", "bf16", "f32")):
+        x, st, ms = timed_solve(lat, b, params(wc, sp, True, basis_prec=qp), torch)
         rec[name] = {"ms": ms, "iters": st[0]["iters"], "true_rel_residual": st[0]["rel_true_res"],
                      "rel_err_vs_fp64_reference": (torch.linalg.vector_norm(x - xref) / nref).item()}
     out["solve_32c64"] = rec
