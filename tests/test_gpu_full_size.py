@@ -1,8 +1,9 @@
 """GPU solves at the full sizes of the benchmark workloads, each checked by the oracle's
 FP64 D_w on sampled right-hand sides (Sec. 4 and 6: SAP-preconditioned FGCR to a true
 residual of 1e-10): the 12 spin-colour point sources on 24^3 x 48 in the configuration the
-batched benchmark times (FP32 arithmetic on FP16 storage, even/odd block solver, FP64
-FGCR, graph capture), the uneven batch {8^3 x 16, 12^3 x 24, 16^3 x 32} with four Gaussian
+batched benchmark times (FP32 arithmetic on BF16 storage, even/odd block solver, FGCR with
+the single-precision recursion of an F32 basis, graph capture) and with FP16 storage and
+an FP64 basis, the uneven batch {8^3 x 16, 12^3 x 24, 16^3 x 32} with four Gaussian
 right-hand sides each on block shapes chosen by the block-shape autotuner, and the
 rhs-tile autotuner."""
 import numpy as np
@@ -26,11 +27,13 @@ def _valid_block(dims, block):
     return vol <= 256 and all(L % b == 0 and (L // b) % 2 == 0 for L, b in zip(dims, block))
 
 
-def test_point_sources_24c48_batched_as_benchmarked():
+@pytest.mark.parametrize("storage,basis", [("bf16", "f32"), ("f16", "f64")])
+def test_point_sources_24c48_batched_as_benchmarked(storage, basis):
     dims, block = (48, 24, 24, 24), (4, 4, 4, 4)
     lat = lattice(dims, block, M0, CSW)
     b = synth.point_sources(dims)
-    x, st = lat.solve(to_dev(b), nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec="f16", eo=1, use_graph=1)
+    x, st = lat.solve(to_dev(b), nkv=16, ncy=5, nmr=4, tol=1e-10, sap_prec=storage, eo=1, use_graph=1,
+                      basis_prec=basis)
     assert all(s["status"] == 0 and s["rel_true_res"] <= 1e-10 for s in st)
     x = to_np(x)
     U, A = gauge(dims), clover(dims, M0, CSW)
