@@ -108,7 +108,8 @@ def test_fp64_dirac_tile_beyond_the_lds_stage():
 @pytest.mark.timeout(900)
 def test_solves_32c64_checked_by_the_oracle():
     """32^3 x 64 (Sec. 6's production lattice): the mixed solves on FP32, FP16 and BF16
-    storage and an independent FP64 reference (the plain MR block solver, tolerance 1e-12,
+    storage (BF16 also with the single-precision recursion of an F32 basis) and an
+    independent FP64 reference (the plain MR block solver, tolerance 1e-12,
     a different iteration from the mixed solves' even/odd block solver) all have their true
     residual recomputed with the oracle's D over the whole lattice (time slabs); the mixed
     solutions' error against the reference stays within the condition-number bound."""
@@ -120,8 +121,8 @@ def test_solves_32c64_checked_by_the_oracle():
     xr, sr = lat.solve(to_dev(b), sap_prec="f64", eo=0, tol=1e-12)
     assert sr[0]["status"] == 0
     xs, st = [to_np(xr)], [sr[0]]
-    for sp in ("f32", "f16", "bf16"):
-        x, s = lat.solve(to_dev(b), sap_prec=sp, eo=1, tol=1e-10)
+    for sp, qp in (("f32", "f64"), ("f16", "f64"), ("bf16", "f64"), ("bf16", "f32")):
+        x, s = lat.solve(to_dev(b), sap_prec=sp, eo=1, tol=1e-10, basis_prec=qp)
         assert s[0]["status"] == 0
         xs.append(to_np(x))
         st.append(s[0])
